@@ -1,0 +1,239 @@
+"""CPU oracle for RRR-set sampling (test infrastructure only).
+
+Only the test suite, the package smoke check and the benchmark's CPU-baseline
+leg may import this package.  The GPU library never links, loads or calls it,
+and it imports nothing from the GPU library.
+
+``rrr_oracle.c`` is the plain C reference (one textbook reverse BFS per
+sample, Definition 2); this module loads it with ctypes, and adds the
+work-accounting formulas of Section 3.1/3.2 in numpy.  ``pytwin`` is a second,
+pure-Python implementation for tiny graphs.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rrr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OR_OK = 0
+OR_EINVAL = -1
+OR_ENOMEM = -2
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle into ``oracle/liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-Wall", "-Wextra", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    vp = ctypes.c_void_p
+    lib.or_thr32.argtypes = [ctypes.c_float]
+    lib.or_thr32.restype = u32
+    lib.or_philox4x32_10.argtypes = [vp, vp, vp]
+    lib.or_philox4x32_10.restype = None
+    lib.or_coin_word.argtypes = [u64, u64, u64]
+    lib.or_coin_word.restype = u32
+    lib.or_edge_live.argtypes = [u64, u64, u64, u32]
+    lib.or_edge_live.restype = i32
+    lib.or_start_vertex.argtypes = [u64, u64, u32]
+    lib.or_start_vertex.restype = u32
+    lib.or_graph_build.argtypes = [u32, u64, vp, vp, vp, ctypes.POINTER(i32)]
+    lib.or_graph_build.restype = vp
+    lib.or_graph_free.argtypes = [vp]
+    lib.or_graph_free.restype = None
+    lib.or_graph_n.argtypes = [vp]
+    lib.or_graph_n.restype = u32
+    lib.or_graph_m.argtypes = [vp]
+    lib.or_graph_m.restype = u64
+    lib.or_graph_export.argtypes = [vp, vp, vp, vp]
+    lib.or_graph_export.restype = None
+    lib.or_sample_ids.argtypes = [vp, u64, vp, u64, i32, ctypes.POINTER(i32)]
+    lib.or_sample_ids.restype = vp
+    lib.or_result_free.argtypes = [vp]
+    lib.or_result_free.restype = None
+    lib.or_result_count.argtypes = [vp]
+    lib.or_result_count.restype = u64
+    lib.or_result_total.argtypes = [vp]
+    lib.or_result_total.restype = u64
+    lib.or_result_export.argtypes = [vp, vp, vp, vp, vp]
+    lib.or_result_export.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def thr32(p: float) -> int:
+    """Threshold of an fp32 probability (0xFFFFFFFF = always live)."""
+    return int(_load().or_thr32(float(np.float32(p))))
+
+
+def philox4x32_10(ctr, key) -> tuple[int, int, int, int]:
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return tuple(int(x) for x in out)
+
+
+def coin_word(seed: int, s: int, e: int) -> int:
+    return int(_load().or_coin_word(seed, s, e))
+
+
+def edge_live(seed: int, s: int, e: int, thr: int) -> bool:
+    return bool(_load().or_edge_live(seed, s, e, thr))
+
+
+def start_vertex(seed: int, s: int, n: int) -> int:
+    return int(_load().or_start_vertex(seed, s, n))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int):
+        super().__init__(f"oracle status {status}")
+        self.status = status
+
+
+@dataclass
+class RRRSets:
+    """Sampled sets in CSR form plus per-member BFS distance and per-sample TE."""
+    sample_ids: np.ndarray   # uint64[count]
+    offsets: np.ndarray      # uint64[count+1]
+    members: np.ndarray      # uint32[total], ascending within each set
+    dist: np.ndarray         # int32[total]
+    te: np.ndarray           # uint64[count], sum of member in-degrees
+
+    def set_of(self, i: int) -> np.ndarray:
+        return self.members[self.offsets[i]:self.offsets[i + 1]]
+
+    def __len__(self) -> int:
+        return len(self.sample_ids)
+
+
+class Graph:
+    """Oracle-side graph: canonical incoming adjacency built from an edge list."""
+
+    def __init__(self, n: int, src, dst, prob):
+        lib = _load()
+        self._src = np.ascontiguousarray(src, dtype=np.uint32)
+        self._dst = np.ascontiguousarray(dst, dtype=np.uint32)
+        self._prob = np.ascontiguousarray(prob, dtype=np.float32)
+        m = len(self._src)
+        if len(self._dst) != m or len(self._prob) != m:
+            raise ValueError("src, dst and prob must have equal length")
+        st = ctypes.c_int(0)
+        h = lib.or_graph_build(n, m, _ptr(self._src) if m else None, _ptr(self._dst) if m else None,
+                               _ptr(self._prob) if m else None, ctypes.byref(st))
+        if not h:
+            raise OracleError(st.value)
+        self._h = h
+        self.n = int(n)
+        self.m = int(m)
+        self._adj = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().or_graph_free(h)
+            self._h = None
+
+    def incoming(self):
+        """(in_begin uint64[n+1], in_src uint32[m], in_thr uint32[m]) in canonical order."""
+        if self._adj is None:
+            b = np.zeros(self.n + 1, dtype=np.uint64)
+            s = np.zeros(max(self.m, 1), dtype=np.uint32)
+            t = np.zeros(max(self.m, 1), dtype=np.uint32)
+            _load().or_graph_export(self._h, _ptr(b), _ptr(s), _ptr(t))
+            self._adj = (b, s[: self.m], t[: self.m])
+        return self._adj
+
+    def indegree(self) -> np.ndarray:
+        b = self.incoming()[0]
+        return (b[1:] - b[:-1]).astype(np.uint64)
+
+    def sample_ids(self, seed: int, ids, nthreads: int = 1) -> RRRSets:
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        lib = _load()
+        st = ctypes.c_int(0)
+        r = lib.or_sample_ids(self._h, seed, _ptr(ids) if len(ids) else None, len(ids),
+                              int(nthreads), ctypes.byref(st))
+        if not r:
+            raise OracleError(st.value)
+        try:
+            count = int(lib.or_result_count(r))
+            total = int(lib.or_result_total(r))
+            offsets = np.zeros(count + 1, dtype=np.uint64)
+            members = np.zeros(max(total, 1), dtype=np.uint32)
+            dist = np.zeros(max(total, 1), dtype=np.int32)
+            te = np.zeros(max(count, 1), dtype=np.uint64)
+            lib.or_result_export(r, _ptr(offsets), _ptr(members), _ptr(dist), _ptr(te))
+        finally:
+            lib.or_result_free(r)
+        return RRRSets(ids, offsets, members[:total], dist[:total], te[:count])
+
+    def sample(self, seed: int, n_samples: int, first_sample: int = 0,
+               nthreads: int = 1) -> RRRSets:
+        ids = np.arange(first_sample, first_sample + n_samples, dtype=np.uint64)
+        return self.sample_ids(seed, ids, nthreads)
+
+
+def fused_edge_accesses(graph: Graph, sets: RRRSets, colors: int) -> int:
+    """Edge accesses of a level-synchronous fused traversal (Section 3.2).
+
+    Samples are grouped into batches of ``colors`` consecutive entries of
+    ``sets`` (which must hold consecutive sample ids starting at a batch
+    boundary).  Within a batch, a vertex v is expanded once per distinct BFS
+    level at which any colour of the batch reaches it, and each expansion
+    examines all indeg(v) incoming edges.  With colors == 1 this equals the
+    total TE of unfused traversals (Theorem 1 holds with equality).
+    """
+    indeg = graph.indegree()
+    total = 0
+    count = len(sets)
+    for b0 in range(0, count, colors):
+        b1 = min(count, b0 + colors)
+        lo, hi = int(sets.offsets[b0]), int(sets.offsets[b1])
+        v = sets.members[lo:hi].astype(np.uint64)
+        d = sets.dist[lo:hi].astype(np.uint64)
+        pairs = np.unique((v << np.uint64(32)) | d)
+        verts = (pairs >> np.uint64(32)).astype(np.int64)
+        total += int(indeg[verts].sum())
+    return total
+
+
+def fused_frontier_entries(sets: RRRSets, colors: int) -> int:
+    """Number of (batch, level, vertex) frontier entries of the same traversal."""
+    total = 0
+    count = len(sets)
+    for b0 in range(0, count, colors):
+        b1 = min(count, b0 + colors)
+        lo, hi = int(sets.offsets[b0]), int(sets.offsets[b1])
+        v = sets.members[lo:hi].astype(np.uint64)
+        d = sets.dist[lo:hi].astype(np.uint64)
+        total += len(np.unique((v << np.uint64(32)) | d))
+    return total
