@@ -1,0 +1,206 @@
+/*
+ * bpt.h - C ABI of libbpt: fused breadth-first probabilistic traversals (BPTs)
+ * that sample random reverse-reachable (RRR) sets under the Independent
+ * Cascade (IC) model on an AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (paper Section 2, Definitions 1 and 2): a directed graph
+ * G = (V, E) with a probability p(e) on each edge is given.  An RRR set is
+ * drawn by picking a start vertex v uniformly at random, keeping every edge e
+ * independently with probability p(e), and collecting every vertex u that
+ * has a directed path u -> ... -> v through kept edges.  Many such sets are
+ * the input of influence maximization by reverse influence sampling.
+ *
+ * Method (paper Section 3, Listing 1): the traversals of C samples (C =
+ * colors_per_batch, one bit per sample, "colour") are fused into one
+ * breadth-first frontier that carries a C-bit mask per vertex, so a vertex
+ * reached by several samples at the same depth has its in-edges expanded
+ * once for all of them.
+ *
+ * Determinism contract.  Each sample s draws its coins from Philox4x32-10
+ * (Salmon et al., SC 2011) keyed on (seed, s, canonical edge id), so the
+ * result depends only on the edge set with its probabilities, n, the sample
+ * ids and the seed.  It is bit-identical for every colors_per_batch, for the
+ * fused and the unfused traversal, for any launch shape and across runs.
+ *
+ * Definitions used throughout:
+ *   canonical edge id   rank of (dst, src) in ascending order (input order is
+ *                       irrelevant).
+ *   threshold           thr(e) = floor(p(e) * 2^32) for p < 1, 0xFFFFFFFF for
+ *                       p = 1.  Edge e is live for sample s iff thr(e) ==
+ *                       0xFFFFFFFF or r < thr(e), where r is word (e & 3) of
+ *                       Philox(counter = (e >> 2, s mod 2^32, s >> 32, 0),
+ *                       key = (seed mod 2^32, seed >> 32)).
+ *   start vertex        word (s & 3) of Philox(counter = ((s >> 2) mod 2^32,
+ *                       s >> 34, 0, 1), same key), mapped to (r * n) >> 32.
+ *   RRR set of s        ascending vertex ids u with a live path u -> start_s
+ *                       (the start itself included).
+ *
+ * Errors.  Functions that return a pointer return NULL on failure; functions
+ * that return int return one of the BPT_* status codes.  Either way the
+ * calling thread's last status and a message are available through
+ * bpt_last_status() / bpt_last_error().  No function aborts the process.
+ *
+ * Threads.  A graph is immutable once created; several threads may sample
+ * from the same graph at once (each call takes its own workspace).
+ */
+#ifndef BPT_H
+#define BPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BPT_OK 0
+#define BPT_EINVAL (-1)   /* invalid argument                                  */
+#define BPT_ENOMEM (-2)   /* host or device allocation failed                  */
+#define BPT_EDEVICE (-3)  /* HIP runtime error or no usable gfx950 device      */
+#define BPT_ERANGE (-4)   /* caller's output buffer too small (size reported)  */
+#define BPT_EINTERNAL (-5)/* a device-side consistency check failed            */
+
+/* Probability layouts detected when a graph is created. */
+#define BPT_PROB_UNIFORM 0 /* one threshold for every edge                      */
+#define BPT_PROB_ROW 1     /* thresholds depend only on the destination vertex  */
+#define BPT_PROB_EDGE 2    /* one threshold per edge                            */
+
+/* Flags of bpt_sample_rrr_device(). */
+#define BPT_FLAG_UNFUSED 1u /* one traversal per sample (the unfused baseline)  */
+
+typedef struct bpt_graph bpt_graph; /* opaque, device-resident, immutable */
+typedef struct bpt_rrr bpt_rrr;     /* opaque, host-resident CSR of RRR sets */
+
+/* Work accounting of one sampling call (paper Section 3.1-3.2 terms). */
+typedef struct bpt_counters {
+    uint64_t samples;          /* RRR sets produced                                    */
+    uint64_t members;          /* sum over samples of |R_s|                             */
+    uint64_t sample_edges;     /* TE: sum over samples of the in-degrees of R_s members
+                                  = edges an unfused traversal examines                  */
+    uint64_t edge_accesses;    /* EA: in-edges examined by the traversal actually run
+                                  (one row scan per frontier entry)                     */
+    uint64_t frontier_entries; /* (batch, level, vertex) frontier entries expanded      */
+    uint64_t philox_blocks;    /* Philox4x32-10 evaluations for edge coins              */
+    uint64_t live_coins;       /* coins that came up live                               */
+    uint64_t levels;           /* sum over batches of BFS levels                        */
+    uint64_t max_levels;       /* deepest batch                                         */
+    uint64_t batches;          /* batches (fused) or traversals (unfused) run           */
+} bpt_counters;
+
+/* ------------------------------------------------------------------------
+ * bpt_create_graph - build the device-resident graph store (paper Section 2:
+ * G = (V, E) with p(e); Listing 1 walks the edges of a frontier vertex, which
+ * for RRR sets are its in-edges).
+ *
+ *   n      number of vertices, 1 <= n < 2^32.
+ *   m      number of edges, m < 2^32 - 4.
+ *   src    host array, m entries: tail u of edge i (u -> dst[i]); u < n.
+ *   dst    host array, m entries: head v of edge i; v < n.
+ *   prob   host array, m entries: p(e) in [0, 1] (fp32, not NaN); the
+ *          probability that u activates v (IC model).
+ *   The three arrays are copied; the caller keeps ownership.  They may be
+ *   NULL when m == 0.
+ *
+ * Stores the transposed CSR on the current HIP device: row v lists the
+ * sources u of v's in-edges in ascending order (canonical edge ids), plus
+ * thresholds in the most compact of the BPT_PROB_* layouts.  Self-loops are
+ * accepted (they never change a set).
+ *
+ * Returns NULL on error: BPT_EINVAL (n == 0, m too large, NULL array with
+ * m > 0, vertex out of range, probability NaN or outside [0, 1], repeated
+ * (src, dst) pair), BPT_ENOMEM, BPT_EDEVICE.  Free with bpt_free().
+ * ---------------------------------------------------------------------- */
+bpt_graph* bpt_create_graph(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
+                            const float* prob);
+
+/* ------------------------------------------------------------------------
+ * bpt_sample_rrr - sample RRR sets 0 .. n_samples-1 with fused BPTs
+ * (paper Section 3, Listing 1) and return them in host memory.
+ *
+ *   g                 graph from bpt_create_graph.
+ *   n_samples         number of RRR sets, < 2^34.  0 gives an empty result.
+ *   colors_per_batch  traversals fused per batch: 64, 128, 256, 512 or 1024;
+ *                     0 lets the library choose.  Does not change the result.
+ *   seed              Philox key.
+ *
+ * Returns a host-resident CSR (see bpt_rrr_* accessors), or NULL on error:
+ * BPT_EINVAL (NULL graph, bad colors_per_batch, n_samples >= 2^34),
+ * BPT_ENOMEM, BPT_EDEVICE, BPT_EINTERNAL.  Free with bpt_free().  The result
+ * does not depend on the graph staying alive.
+ * ---------------------------------------------------------------------- */
+bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_batch,
+                        uint64_t seed);
+
+/* Frees a bpt_graph or a bpt_rrr (the handle carries its type).  NULL is a
+ * no-op.  Sets BPT_EINVAL if the handle is not one of the two. */
+void bpt_free(void* handle);
+
+/* Accessors of a result.  offsets has num_samples+1 entries; the members of
+ * sample i are vertices[offsets[i] .. offsets[i+1]), ascending.  The arrays
+ * belong to the result and stay valid until bpt_free(result). */
+uint64_t bpt_rrr_num_samples(const bpt_rrr* r);
+uint64_t bpt_rrr_num_members(const bpt_rrr* r);
+const uint64_t* bpt_rrr_offsets(const bpt_rrr* r);
+const uint32_t* bpt_rrr_vertices(const bpt_rrr* r);
+
+/* Last status / message of the calling thread (message valid until the
+ * thread's next libbpt call). */
+int bpt_last_status(void);
+const char* bpt_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Extensions.
+ * ---------------------------------------------------------------------- */
+
+/* bpt_sample_rrr_device - sample RRR sets first_sample .. first_sample +
+ * n_samples - 1 into caller-owned DEVICE buffers, on a caller's stream.
+ *
+ *   first_sample      id of the first sample (a shard of a larger job gives
+ *                     its own range; the sets equal those of one big call).
+ *   n_samples         as in bpt_sample_rrr.
+ *   colors_per_batch  as in bpt_sample_rrr (ignored with BPT_FLAG_UNFUSED).
+ *   flags             0, or BPT_FLAG_UNFUSED for one traversal per sample.
+ *   stream            hipStream_t to run on (NULL = the default stream).
+ *   d_offsets         device array of n_samples+1 uint64: written with the
+ *                     CSR offsets (d_offsets[0] = 0).
+ *   d_vertices        device array of `capacity` uint32: written with the
+ *                     members, sample after sample, ascending within each.
+ *   capacity          entries available in d_vertices.
+ *   total_out         host pointer, required: receives the total number of
+ *                     members (= d_offsets[n_samples]).
+ *   counters          host pointer or NULL: receives the work accounting.
+ *
+ * Blocks the calling thread until the work on `stream` is done.  If
+ * capacity < total, returns BPT_ERANGE with *total_out set and d_vertices
+ * untouched (d_offsets is written); call again with a larger buffer.  Other
+ * errors: BPT_EINVAL (NULL graph/pointers, bad colors or flags), BPT_ENOMEM,
+ * BPT_EDEVICE, BPT_EINTERNAL.
+ */
+int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_samples,
+                          uint32_t colors_per_batch, uint64_t seed, uint32_t flags, void* stream,
+                          uint64_t* d_offsets, uint32_t* d_vertices, uint64_t capacity,
+                          uint64_t* total_out, bpt_counters* counters);
+
+/* Graph facts: vertices, edges, probability layout (BPT_PROB_*).  Any output
+ * pointer may be NULL.  Returns BPT_OK or BPT_EINVAL. */
+int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_layout);
+
+/* Colour count the library uses for colors_per_batch = 0 on this graph for a
+ * job of n_samples samples (64 .. 1024). */
+uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples);
+
+/* Host builds of the library's own arithmetic, for checks on machines
+ * without a GPU: the threshold of an fp32 probability, the coin word of
+ * (seed, s, e) and the start vertex of sample s on n vertices, exactly as the
+ * device computes them (definitions above). */
+uint32_t bpt_thr32(float p);
+uint32_t bpt_coin_word(uint64_t seed, uint64_t sample, uint64_t edge);
+uint32_t bpt_start_vertex(uint64_t seed, uint64_t sample, uint32_t n);
+
+/* Library version string. */
+const char* bpt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPT_H */

@@ -1,0 +1,269 @@
+"""Python binding of libbpt: fused breadth-first probabilistic traversals that
+sample RRR sets on an AMD MI355X (gfx950).
+
+Argument marshalling only.  Every step of the sampling runs in the HIP
+library ``libbpt.so`` (built by ``paper_2311_10201_amd.build``); calls raise
+``RuntimeError`` if the library is missing.  Function names follow the C ABI
+declared in ``include/bpt.h``.  PyTorch tensors may be passed wherever a
+device buffer or stream is expected (``bpt_sample_rrr_device``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "BPT_OK", "BPT_EINVAL", "BPT_ENOMEM", "BPT_EDEVICE", "BPT_ERANGE", "BPT_EINTERNAL",
+    "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED",
+    "BptError", "Counters", "Graph", "RRRResult",
+    "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_graph_info",
+    "bpt_default_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
+    "bpt_last_status", "bpt_last_error", "library_path", "load_library",
+]
+
+BPT_OK = 0
+BPT_EINVAL = -1
+BPT_ENOMEM = -2
+BPT_EDEVICE = -3
+BPT_ERANGE = -4
+BPT_EINTERNAL = -5
+BPT_PROB_UNIFORM = 0
+BPT_PROB_ROW = 1
+BPT_PROB_EDGE = 2
+BPT_FLAG_UNFUSED = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbpt.so")
+_lib = None
+
+# every symbol include/bpt.h declares
+EXPORTED_SYMBOLS = (
+    "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_rrr_num_samples", "bpt_rrr_num_members",
+    "bpt_rrr_offsets", "bpt_rrr_vertices", "bpt_last_status", "bpt_last_error", "bpt_sample_rrr_device",
+    "bpt_graph_info", "bpt_default_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
+)
+
+
+class _Counters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "samples", "members", "sample_edges", "edge_accesses", "frontier_entries", "philox_blocks",
+        "live_coins", "levels", "max_levels", "batches")]
+
+
+@dataclass
+class Counters:
+    samples: int = 0
+    members: int = 0
+    sample_edges: int = 0
+    edge_accesses: int = 0
+    frontier_entries: int = 0
+    philox_blocks: int = 0
+    live_coins: int = 0
+    levels: int = 0
+    max_levels: int = 0
+    batches: int = 0
+
+
+class BptError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libbpt error {status}: {message}")
+        self.status = status
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Loads libbpt.so; raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_2311_10201_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    u32, u64, i32, vp, cp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p
+    sig = {
+        "bpt_create_graph": (vp, [u32, u64, vp, vp, vp]),
+        "bpt_sample_rrr": (vp, [vp, u64, u32, u64]),
+        "bpt_free": (None, [vp]),
+        "bpt_rrr_num_samples": (u64, [vp]),
+        "bpt_rrr_num_members": (u64, [vp]),
+        "bpt_rrr_offsets": (vp, [vp]),
+        "bpt_rrr_vertices": (vp, [vp]),
+        "bpt_last_status": (i32, []),
+        "bpt_last_error": (cp, []),
+        "bpt_sample_rrr_device": (i32, [vp, u64, u64, u32, u64, u32, vp, vp, vp, u64,
+                                        ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
+        "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
+        "bpt_default_colors": (u32, [vp, u64]),
+        "bpt_thr32": (u32, [ctypes.c_float]),
+        "bpt_coin_word": (u32, [u64, u64, u64]),
+        "bpt_start_vertex": (u32, [u64, u64, u32]),
+        "bpt_version": (cp, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _raise_last():
+    lib = load_library()
+    raise BptError(int(lib.bpt_last_status()), lib.bpt_last_error().decode(errors="replace"))
+
+
+def _addr(x) -> int | None:
+    """Device or host address of a torch tensor, numpy array or integer."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream)
+    raise TypeError(f"not a stream: {type(s)}")
+
+
+class Graph:
+    """Owns a bpt_graph handle."""
+
+    def __init__(self, handle: int, n: int, m: int):
+        self.handle = handle
+        self.n = n
+        self.m = m
+
+    def close(self):
+        if self.handle:
+            load_library().bpt_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class RRRResult:
+    offsets: np.ndarray   # uint64[n_samples + 1]
+    vertices: np.ndarray  # uint32[offsets[-1]]
+
+    def set_of(self, i: int) -> np.ndarray:
+        return self.vertices[self.offsets[i]:self.offsets[i + 1]]
+
+    def __len__(self) -> int:
+        return len(self.offsets) - 1
+
+
+def bpt_create_graph(n: int, src, dst, prob) -> Graph:
+    lib = load_library()
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    prob = np.ascontiguousarray(prob, dtype=np.float32)
+    m = len(src)
+    if len(dst) != m or len(prob) != m:
+        raise ValueError("src, dst and prob must have equal length")
+    h = lib.bpt_create_graph(n, m, _addr(src) if m else None, _addr(dst) if m else None,
+                             _addr(prob) if m else None)
+    if not h:
+        _raise_last()
+    return Graph(h, n, m)
+
+
+def bpt_free(obj) -> None:
+    if isinstance(obj, Graph):
+        obj.close()
+    else:
+        load_library().bpt_free(obj)
+
+
+def bpt_sample_rrr(graph: Graph, n_samples: int, colors_per_batch: int, seed: int) -> RRRResult:
+    """Host-resident RRR sets of samples 0 .. n_samples-1 (copied out of the handle)."""
+    lib = load_library()
+    r = lib.bpt_sample_rrr(graph.handle, n_samples, colors_per_batch, seed)
+    if not r:
+        _raise_last()
+    try:
+        ns = int(lib.bpt_rrr_num_samples(r))
+        total = int(lib.bpt_rrr_num_members(r))
+        off = np.ctypeslib.as_array(ctypes.cast(lib.bpt_rrr_offsets(r), ctypes.POINTER(ctypes.c_uint64)),
+                                    shape=(ns + 1,)).copy()
+        if total:
+            ver = np.ctypeslib.as_array(ctypes.cast(lib.bpt_rrr_vertices(r), ctypes.POINTER(ctypes.c_uint32)),
+                                        shape=(total,)).copy()
+        else:
+            ver = np.zeros(0, dtype=np.uint32)
+    finally:
+        lib.bpt_free(r)
+    return RRRResult(off, ver)
+
+
+def bpt_sample_rrr_device(graph: Graph, first_sample: int, n_samples: int, colors_per_batch: int, seed: int,
+                          flags: int, stream, d_offsets, d_vertices, capacity: int):
+    """Samples into caller-owned device buffers.  Returns (status, total, Counters);
+    status is BPT_OK or BPT_ERANGE (buffer too small, total reports the need)."""
+    lib = load_library()
+    total = ctypes.c_uint64(0)
+    cnt = _Counters()
+    st = lib.bpt_sample_rrr_device(graph.handle, first_sample, n_samples, colors_per_batch, seed, flags,
+                                   _stream(stream), _addr(d_offsets), _addr(d_vertices), capacity,
+                                   ctypes.byref(total), ctypes.byref(cnt))
+    if st not in (BPT_OK, BPT_ERANGE):
+        _raise_last()
+    return st, int(total.value), Counters(**{k: int(getattr(cnt, k)) for k, _ in _Counters._fields_})
+
+
+def bpt_graph_info(graph: Graph):
+    lib = load_library()
+    n, m, lay = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+    if lib.bpt_graph_info(graph.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(lay)) != BPT_OK:
+        _raise_last()
+    return int(n.value), int(m.value), int(lay.value)
+
+
+def bpt_default_colors(graph: Graph, n_samples: int) -> int:
+    return int(load_library().bpt_default_colors(graph.handle, n_samples))
+
+
+def bpt_thr32(p: float) -> int:
+    return int(load_library().bpt_thr32(float(np.float32(p))))
+
+
+def bpt_coin_word(seed: int, sample: int, edge: int) -> int:
+    return int(load_library().bpt_coin_word(seed, sample, edge))
+
+
+def bpt_start_vertex(seed: int, sample: int, n: int) -> int:
+    return int(load_library().bpt_start_vertex(seed, sample, n))
+
+
+def bpt_version() -> str:
+    return load_library().bpt_version().decode()
+
+
+def bpt_last_status() -> int:
+    return int(load_library().bpt_last_status())
+
+
+def bpt_last_error() -> str:
+    return load_library().bpt_last_error().decode(errors="replace")

@@ -1,0 +1,649 @@
+// C ABI of libbpt: handles, error state, workspaces and the sampling driver.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bpt.h"
+#include "bpt_host.hpp"
+#include "bpt_internal.hpp"
+#include "bpt_rng.hpp"
+
+#define BPT_VERSION_STRING "libbpt 0.1 (gfx950)"
+
+namespace bpt {
+namespace {
+
+constexpr uint32_t kGraphMagic = 0x42505447u;  // "BPTG"
+constexpr uint32_t kRrrMagic = 0x42505452u;    // "BPTR"
+constexpr uint32_t kDeadMagic = 0xDEADBEEFu;
+
+thread_local int t_status = BPT_OK;
+thread_local std::string t_message;
+
+void set_status(int st, const std::string& msg) {
+    t_status = st;
+    t_message = msg;
+}
+void set_ok() {
+    t_status = BPT_OK;
+    t_message.clear();
+}
+
+struct HipFail {
+    int status;
+    std::string msg;
+};
+
+#define HIP_TRY(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            throw HipFail{e_ == hipErrorOutOfMemory ? BPT_ENOMEM : BPT_EDEVICE,                  \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)};                    \
+        }                                                                                        \
+    } while (0)
+
+template <typename T>
+T* dev_alloc(size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    HIP_TRY(hipMalloc(&p, bytes));
+    return static_cast<T*>(p);
+}
+
+void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+// One set of traversal state + output staging; a call holds one exclusively.
+struct Workspace {
+    int nw = 0;  // colour words per mask (fused), 0 = unfused
+    uint32_t slots = 0;
+    void* slot_mem = nullptr;
+    FusedSlots fs{};
+    UnfusedSlots us{};
+    Control* ctl = nullptr;
+    Control* ctl_host = nullptr;  // pinned
+    uint32_t* pool = nullptr;
+    uint64_t pool_cap = 0;
+    uint32_t* counts = nullptr;
+    unsigned long long* where = nullptr;
+    uint64_t sample_cap = 0;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    unsigned long long* out_offsets = nullptr;  // host-API device output
+    uint64_t out_offsets_cap = 0;
+    uint32_t* out_vertices = nullptr;
+    uint64_t out_vertices_cap = 0;
+
+    ~Workspace() {
+        dev_free(slot_mem);
+        dev_free(ctl);
+        if (ctl_host) (void)hipHostFree(ctl_host);
+        dev_free(pool);
+        dev_free(counts);
+        dev_free(where);
+        dev_free(scratch);
+        dev_free(out_offsets);
+        dev_free(out_vertices);
+    }
+};
+
+}  // namespace
+}  // namespace bpt
+
+struct bpt_graph {
+    uint32_t magic;
+    int device;
+    int cus;
+    uint32_t n;
+    uint64_t m;
+    uint32_t layout;
+    uint32_t thr_uniform;
+    uint32_t* d_rowptr;
+    uint32_t* d_col;
+    uint32_t* d_thr_row;
+    uint32_t* d_thr_edge;
+    std::mutex mu;
+    std::vector<bpt::Workspace*> idle;
+};
+
+struct bpt_rrr {
+    uint32_t magic;
+    uint64_t num_samples;
+    uint64_t total;
+    uint64_t* offsets;
+    uint32_t* vertices;
+};
+
+namespace bpt {
+namespace {
+
+bool valid_colors(uint32_t c) { return c == 64 || c == 128 || c == 256 || c == 512 || c == 1024; }
+
+DevGraph dev_graph(const bpt_graph* g) {
+    DevGraph d;
+    d.rowptr = g->d_rowptr;
+    d.col = g->d_col;
+    d.thr_row = g->d_thr_row;
+    d.thr_edge = g->d_thr_edge;
+    d.thr_uniform = g->thr_uniform;
+    d.prob_layout = g->layout;
+    d.n = g->n;
+    d.m = (uint32_t)g->m;
+    return d;
+}
+
+size_t fused_slot_bytes(uint32_t n, int nw) {
+    const size_t N = n;
+    size_t b = 0;
+    b += N * nw * 8;        // visited
+    b += 2 * N * nw * 8;    // frontier (two levels)
+    b += (nw > 1) ? N * 4 : 0;  // stamp
+    b += 2 * N * 4;         // queue
+    b += N * 4;             // touched
+    b += bitmap_words(n) * 8;  // touched bitmap
+    return b;
+}
+
+size_t unfused_slot_bytes(uint32_t n) { return bitmap_words(n) * 8 + (size_t)n * 4; }
+
+size_t memory_budget() {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return (size_t)8 << 30;
+    return std::min(free_b / 3, (size_t)96 << 30);
+}
+
+// Allocates and zeroes the traversal state of a new workspace.
+Workspace* make_workspace(bpt_graph* g, int nw) {
+    Workspace* ws = new Workspace();
+    ws->nw = nw;
+    try {
+        const uint32_t n = g->n;
+        const size_t budget = memory_budget();
+        char* p;
+        if (nw > 0) {
+            const size_t per = fused_slot_bytes(n, nw) + 256;
+            size_t want = (size_t)g->cus * 2;
+            want = std::min(want, std::max<size_t>(1, budget / per));
+            ws->slots = (uint32_t)std::max<size_t>(1, want);
+            const size_t S = ws->slots, N = n;
+            const size_t words = bitmap_words(n);
+            size_t bytes = S * per + S * 4 + 1024;
+            ws->slot_mem = dev_alloc<char>(bytes);
+            HIP_TRY(hipMemset(ws->slot_mem, 0, bytes));
+            p = static_cast<char*>(ws->slot_mem);
+            auto take = [&](size_t sz) {
+                char* q = p;
+                p += (sz + 255) & ~(size_t)255;
+                return q;
+            };
+            ws->fs.visited = reinterpret_cast<unsigned long long*>(take(S * N * nw * 8));
+            ws->fs.frontier = reinterpret_cast<unsigned long long*>(take(S * 2 * N * nw * 8));
+            ws->fs.stamp = reinterpret_cast<uint32_t*>(take(nw > 1 ? S * N * 4 : 4));
+            ws->fs.queue = reinterpret_cast<uint32_t*>(take(S * 2 * N * 4));
+            ws->fs.touched = reinterpret_cast<uint32_t*>(take(S * N * 4));
+            ws->fs.tbits = reinterpret_cast<unsigned long long*>(take(S * words * 8));
+            ws->fs.slot_tag = reinterpret_cast<uint32_t*>(take(S * 4));
+            ws->fs.slots = ws->slots;
+        } else {
+            const size_t per = unfused_slot_bytes(n) + 512;
+            size_t want = (size_t)g->cus * 16;  // wavefronts
+            want = std::min(want, std::max<size_t>(4, budget / per));
+            want = std::max<size_t>(4, want / 4 * 4);  // whole workgroups of 4 waves
+            ws->slots = (uint32_t)want;
+            const size_t S = ws->slots;
+            const size_t words = bitmap_words(n);
+            size_t bytes = S * per + 1024;
+            ws->slot_mem = dev_alloc<char>(bytes);
+            HIP_TRY(hipMemset(ws->slot_mem, 0, bytes));
+            p = static_cast<char*>(ws->slot_mem);
+            ws->us.vbits = reinterpret_cast<unsigned long long*>(p);
+            p += ((S * words * 8) + 255) & ~(size_t)255;
+            ws->us.log = reinterpret_cast<uint32_t*>(p);
+            ws->us.slots = ws->slots;
+        }
+        ws->ctl = dev_alloc<Control>(1);
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ws->ctl_host), sizeof(Control), hipHostMallocDefault));
+        HIP_TRY(hipDeviceSynchronize());
+    } catch (...) {
+        delete ws;
+        throw;
+    }
+    return ws;
+}
+
+Workspace* acquire(bpt_graph* g, int nw) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (size_t i = 0; i < g->idle.size(); ++i) {
+            if (g->idle[i]->nw == nw) {
+                Workspace* ws = g->idle[i];
+                g->idle.erase(g->idle.begin() + i);
+                return ws;
+            }
+        }
+    }
+    return make_workspace(g, nw);
+}
+
+void release(bpt_graph* g, Workspace* ws) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->idle.push_back(ws);
+}
+
+void ensure_sample_arrays(Workspace* ws, uint64_t n_samples) {
+    if (ws->sample_cap < n_samples) {
+        dev_free(ws->counts);
+        dev_free(ws->where);
+        ws->counts = nullptr;
+        ws->where = nullptr;
+        ws->sample_cap = 0;
+        const uint64_t cap = std::max<uint64_t>(n_samples, 1024);
+        ws->counts = dev_alloc<uint32_t>(cap);
+        ws->where = dev_alloc<unsigned long long>(cap);
+        ws->sample_cap = cap;
+    }
+    const size_t need = finalize_scratch_bytes(n_samples);
+    if (ws->scratch_bytes < need) {
+        dev_free(ws->scratch);
+        ws->scratch = nullptr;
+        ws->scratch_bytes = 0;
+        ws->scratch = dev_alloc<char>(need);
+        ws->scratch_bytes = need;
+    }
+}
+
+void ensure_pool(Workspace* ws, uint64_t entries) {
+    if (ws->pool_cap >= entries) return;
+    dev_free(ws->pool);
+    ws->pool = nullptr;
+    ws->pool_cap = 0;
+    ws->pool = dev_alloc<uint32_t>(entries);
+    ws->pool_cap = entries;
+}
+
+void ensure_out(Workspace* ws, uint64_t n_samples, uint64_t entries) {
+    if (ws->out_offsets_cap < n_samples + 1) {
+        dev_free(ws->out_offsets);
+        ws->out_offsets = nullptr;
+        ws->out_offsets_cap = 0;
+        ws->out_offsets = dev_alloc<unsigned long long>(n_samples + 1);
+        ws->out_offsets_cap = n_samples + 1;
+    }
+    if (ws->out_vertices_cap < entries) {
+        dev_free(ws->out_vertices);
+        ws->out_vertices = nullptr;
+        ws->out_vertices_cap = 0;
+        ws->out_vertices = dev_alloc<uint32_t>(entries);
+        ws->out_vertices_cap = entries;
+    }
+}
+
+struct CallResult {
+    uint64_t total = 0;
+    bpt_counters counters{};
+};
+
+// Runs the traversal and the CSR assembly.  When `own_output` is set the
+// result goes to the workspace's own device buffers (sized to fit).
+int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32_t colors, uint64_t seed,
+                 bool unfused, hipStream_t stream, unsigned long long* d_offsets, uint32_t* d_vertices,
+                 uint64_t capacity, bool own_output, CallResult* res) {
+    ensure_sample_arrays(ws, S);
+    if (ws->pool_cap == 0) {
+        const uint64_t guess = std::max<uint64_t>(1u << 20, S * 32);
+        ensure_pool(ws, std::min<uint64_t>(guess, (uint64_t)g->n * S));
+    }
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        if (own_output) {
+            ensure_out(ws, S, ws->pool_cap);
+            d_offsets = ws->out_offsets;
+            d_vertices = ws->out_vertices;
+            capacity = ws->out_vertices_cap;
+        }
+        HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), stream));
+        Output out;
+        out.counts = ws->counts;
+        out.where = ws->where;
+        out.pool = ws->pool;
+        out.pool_cap = ws->pool_cap;
+        if (!unfused) {
+            FusedArgs a;
+            a.g = dev_graph(g);
+            a.ws = ws->fs;
+            a.out = out;
+            a.ctl = ws->ctl;
+            a.seed = seed;
+            a.first_sample = first;
+            a.n_samples = S;
+            a.colors = colors;
+            a.n_batches = (S + colors - 1) / colors;
+            const int grid = (int)std::min<uint64_t>(ws->slots, a.n_batches);
+            HIP_TRY(launch_fused(a, ws->nw, grid, stream));
+        } else {
+            UnfusedArgs a;
+            a.g = dev_graph(g);
+            a.ws = ws->us;
+            a.out = out;
+            a.ctl = ws->ctl;
+            a.seed = seed;
+            a.first_sample = first;
+            a.n_samples = S;
+            const uint64_t blocks_needed = (S + 3) / 4;
+            const int grid = (int)std::min<uint64_t>(ws->slots / 4, blocks_needed);
+            HIP_TRY(launch_unfused(a, grid, stream));
+        }
+        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, ws->ctl,
+                                ws->scratch, ws->scratch_bytes, stream));
+        HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const Control& c = *ws->ctl_host;
+        if (c.err & kErrPoolOverflow) {
+            const uint64_t need = c.pool_cursor + c.pool_cursor / 8 + 1024;
+            ensure_pool(ws, need);
+            continue;
+        }
+        if (c.err) {
+            set_status(BPT_EINTERNAL, "device consistency check failed (error bits " + std::to_string(c.err) + ")");
+            return BPT_EINTERNAL;
+        }
+        res->total = c.total;
+        bpt_counters& k = res->counters;
+        k.samples = S;
+        k.members = c.stats[kStatMembers];
+        k.sample_edges = c.stats[kStatSampleEdges];
+        k.edge_accesses = c.stats[kStatEdgeAccesses];
+        k.frontier_entries = c.stats[kStatEntries];
+        k.philox_blocks = c.stats[kStatPhilox];
+        k.live_coins = c.stats[kStatLive];
+        k.levels = c.stats[kStatLevels];
+        k.max_levels = c.stats[kStatMaxLevels];
+        k.batches = c.stats[kStatBatches];
+        if (c.total > capacity) {
+            set_status(BPT_ERANGE, "output capacity " + std::to_string(capacity) + " < " + std::to_string(c.total) +
+                                       " members");
+            return BPT_ERANGE;
+        }
+        return BPT_OK;
+    }
+    set_status(BPT_ENOMEM, "output pool kept overflowing");
+    return BPT_ENOMEM;
+}
+
+bpt_graph* check_graph(const void* h) {
+    if (!h) return nullptr;
+    const bpt_graph* g = static_cast<const bpt_graph*>(h);
+    return g->magic == kGraphMagic ? const_cast<bpt_graph*>(g) : nullptr;
+}
+
+uint32_t choose_colors(const bpt_graph* g, uint64_t n_samples) {
+    (void)g;
+    (void)n_samples;
+    return 64;
+}
+
+}  // namespace
+}  // namespace bpt
+
+using namespace bpt;
+
+extern "C" {
+
+bpt_graph* bpt_create_graph(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst, const float* prob) {
+    HostCsr csr;
+    std::string why;
+    const int st = build_host_csr(n, m, src, dst, prob, &csr, &why);
+    if (st != BPT_OK) {
+        set_status(st, why);
+        return nullptr;
+    }
+    bpt_graph* g = nullptr;
+    try {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            set_status(BPT_EDEVICE, std::string("libbpt is built for gfx950; device is ") + prop.gcnArchName);
+            return nullptr;
+        }
+        g = new bpt_graph();
+        g->magic = kGraphMagic;
+        g->device = dev;
+        g->cus = prop.multiProcessorCount;
+        g->n = n;
+        g->m = m;
+        g->layout = csr.layout;
+        g->thr_uniform = csr.thr_uniform;
+        g->d_rowptr = dev_alloc<uint32_t>(csr.rowptr.size());
+        g->d_col = dev_alloc<uint32_t>(csr.col.size());
+        HIP_TRY(hipMemcpy(g->d_rowptr, csr.rowptr.data(), csr.rowptr.size() * 4, hipMemcpyHostToDevice));
+        if (!csr.col.empty())
+            HIP_TRY(hipMemcpy(g->d_col, csr.col.data(), csr.col.size() * 4, hipMemcpyHostToDevice));
+        if (csr.layout == BPT_PROB_ROW) {
+            g->d_thr_row = dev_alloc<uint32_t>(csr.thr_row.size());
+            HIP_TRY(hipMemcpy(g->d_thr_row, csr.thr_row.data(), csr.thr_row.size() * 4, hipMemcpyHostToDevice));
+        } else if (csr.layout == BPT_PROB_EDGE) {
+            g->d_thr_edge = dev_alloc<uint32_t>(csr.thr_edge.size());
+            HIP_TRY(hipMemcpy(g->d_thr_edge, csr.thr_edge.data(), csr.thr_edge.size() * 4, hipMemcpyHostToDevice));
+        }
+    } catch (const HipFail& f) {
+        if (g) {
+            g->magic = kGraphMagic;
+            bpt_free(g);
+        }
+        set_status(f.status, f.msg);
+        return nullptr;
+    } catch (const std::bad_alloc&) {
+        if (g) bpt_free(g);
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    set_ok();
+    return g;
+}
+
+int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_samples, uint32_t colors_per_batch,
+                          uint64_t seed, uint32_t flags, void* stream, uint64_t* d_offsets, uint32_t* d_vertices,
+                          uint64_t capacity, uint64_t* total_out, bpt_counters* counters) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return BPT_EINVAL;
+    }
+    if (!total_out || !d_offsets || (!d_vertices && capacity > 0)) {
+        set_status(BPT_EINVAL, "d_offsets and total_out are required (d_vertices when capacity > 0)");
+        return BPT_EINVAL;
+    }
+    if (flags & ~BPT_FLAG_UNFUSED) {
+        set_status(BPT_EINVAL, "unknown flag bits");
+        return BPT_EINVAL;
+    }
+    const bool unfused = (flags & BPT_FLAG_UNFUSED) != 0;
+    uint32_t colors = colors_per_batch;
+    if (!unfused) {
+        if (colors == 0) colors = choose_colors(gg, n_samples);
+        if (!valid_colors(colors)) {
+            set_status(BPT_EINVAL, "colors_per_batch must be 0, 64, 128, 256, 512 or 1024");
+            return BPT_EINVAL;
+        }
+    }
+    if (n_samples >= kMaxSamples || first_sample >= kMaxSamples || first_sample + n_samples > kMaxSamples) {
+        set_status(BPT_EINVAL, "sample ids must stay below 2^34");
+        return BPT_EINVAL;
+    }
+    Workspace* ws = nullptr;
+    try {
+        HIP_TRY(hipSetDevice(gg->device));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (n_samples == 0) {
+            HIP_TRY(hipMemsetAsync(d_offsets, 0, sizeof(uint64_t), st));
+            HIP_TRY(hipStreamSynchronize(st));
+            *total_out = 0;
+            if (counters) memset(counters, 0, sizeof(*counters));
+            set_ok();
+            return BPT_OK;
+        }
+        ws = acquire(gg, unfused ? 0 : (int)(colors / 64));
+        CallResult res;
+        const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, unfused, st,
+                                    reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity, false,
+                                    &res);
+        release(gg, ws);
+        ws = nullptr;
+        if (rc == BPT_OK || rc == BPT_ERANGE) {
+            *total_out = res.total;
+            if (counters) *counters = res.counters;
+        }
+        if (rc == BPT_OK) set_ok();
+        return rc;
+    } catch (const HipFail& f) {
+        if (ws) release(gg, ws);
+        set_status(f.status, f.msg);
+        return f.status;
+    } catch (const std::bad_alloc&) {
+        if (ws) release(gg, ws);
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return BPT_ENOMEM;
+    }
+}
+
+bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_batch, uint64_t seed) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return nullptr;
+    }
+    uint32_t colors = colors_per_batch == 0 ? choose_colors(gg, n_samples) : colors_per_batch;
+    if (!valid_colors(colors)) {
+        set_status(BPT_EINVAL, "colors_per_batch must be 0, 64, 128, 256, 512 or 1024");
+        return nullptr;
+    }
+    if (n_samples >= kMaxSamples) {
+        set_status(BPT_EINVAL, "n_samples must be below 2^34");
+        return nullptr;
+    }
+    bpt_rrr* r = nullptr;
+    Workspace* ws = nullptr;
+    try {
+        r = new bpt_rrr();
+        r->magic = kRrrMagic;
+        r->num_samples = n_samples;
+        r->offsets = static_cast<uint64_t*>(malloc((n_samples + 1) * sizeof(uint64_t)));
+        if (!r->offsets) throw std::bad_alloc();
+        r->offsets[0] = 0;
+        if (n_samples > 0) {
+            HIP_TRY(hipSetDevice(gg->device));
+            ws = acquire(gg, (int)(colors / 64));
+            CallResult res;
+            const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, false, nullptr, nullptr, nullptr, 0,
+                                        true, &res);
+            if (rc != BPT_OK) {
+                release(gg, ws);
+                bpt_free(r);
+                return nullptr;
+            }
+            r->total = res.total;
+            r->vertices = static_cast<uint32_t*>(malloc(std::max<uint64_t>(res.total, 1) * sizeof(uint32_t)));
+            if (!r->vertices) throw std::bad_alloc();
+            HIP_TRY(hipMemcpy(r->offsets, ws->out_offsets, (n_samples + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+            if (res.total)
+                HIP_TRY(hipMemcpy(r->vertices, ws->out_vertices, res.total * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            release(gg, ws);
+            ws = nullptr;
+        } else {
+            r->total = 0;
+            r->vertices = static_cast<uint32_t*>(malloc(sizeof(uint32_t)));
+            if (!r->vertices) throw std::bad_alloc();
+        }
+    } catch (const HipFail& f) {
+        if (ws) release(gg, ws);
+        if (r) bpt_free(r);
+        set_status(f.status, f.msg);
+        return nullptr;
+    } catch (const std::bad_alloc&) {
+        if (ws) release(gg, ws);
+        if (r) bpt_free(r);
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    set_ok();
+    return r;
+}
+
+void bpt_free(void* handle) {
+    if (!handle) {
+        set_ok();
+        return;
+    }
+    const uint32_t magic = *static_cast<const uint32_t*>(handle);
+    if (magic == kGraphMagic) {
+        bpt_graph* g = static_cast<bpt_graph*>(handle);
+        g->magic = kDeadMagic;
+        (void)hipSetDevice(g->device);
+        for (Workspace* ws : g->idle) delete ws;
+        g->idle.clear();
+        dev_free(g->d_rowptr);
+        dev_free(g->d_col);
+        dev_free(g->d_thr_row);
+        dev_free(g->d_thr_edge);
+        delete g;
+        set_ok();
+    } else if (magic == kRrrMagic) {
+        bpt_rrr* r = static_cast<bpt_rrr*>(handle);
+        r->magic = kDeadMagic;
+        free(r->offsets);
+        free(r->vertices);
+        delete r;
+        set_ok();
+    } else {
+        set_status(BPT_EINVAL, "bpt_free: not a libbpt handle");
+    }
+}
+
+uint64_t bpt_rrr_num_samples(const bpt_rrr* r) { return (r && r->magic == kRrrMagic) ? r->num_samples : 0; }
+uint64_t bpt_rrr_num_members(const bpt_rrr* r) { return (r && r->magic == kRrrMagic) ? r->total : 0; }
+const uint64_t* bpt_rrr_offsets(const bpt_rrr* r) { return (r && r->magic == kRrrMagic) ? r->offsets : nullptr; }
+const uint32_t* bpt_rrr_vertices(const bpt_rrr* r) { return (r && r->magic == kRrrMagic) ? r->vertices : nullptr; }
+
+int bpt_last_status(void) { return t_status; }
+const char* bpt_last_error(void) { return t_message.c_str(); }
+
+int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_layout) {
+    const bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return BPT_EINVAL;
+    }
+    if (n) *n = gg->n;
+    if (m) *m = gg->m;
+    if (prob_layout) *prob_layout = gg->layout;
+    set_ok();
+    return BPT_OK;
+}
+
+uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples) {
+    const bpt_graph* gg = check_graph(g);
+    return choose_colors(gg, n_samples);
+}
+
+uint32_t bpt_thr32(float p) { return threshold_of(p); }
+
+uint32_t bpt_coin_word(uint64_t seed, uint64_t sample, uint64_t edge) {
+    const Block4 b = coin_block((uint32_t)(edge >> 2), sample, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return pick_word(b, (uint32_t)(edge & 3));
+}
+
+uint32_t bpt_start_vertex(uint64_t seed, uint64_t sample, uint32_t n) {
+    return start_of(sample, n, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+const char* bpt_version(void) { return BPT_VERSION_STRING; }
+
+}  // extern "C"

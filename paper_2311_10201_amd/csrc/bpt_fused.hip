@@ -1,0 +1,514 @@
+// Fused breadth-first probabilistic traversals (paper Section 3, Listing 1)
+// for gfx950.
+//
+// One persistent workgroup owns one "slot" of traversal state and processes
+// batches of C = 64*NW samples (colours) one after another, claiming batch
+// ids from a device counter until none are left.  Within a batch the
+// traversal is level-synchronous (Section 3.2):
+//
+//   frontier entry   a vertex v with the mask of colours that reached it at
+//                    the current depth (Listing 1's frontier[v]).
+//   expansion        every in-edge e = (u -> v) of the entry is tried for
+//                    every colour of the mask.  Work items are (entry,
+//                    4-edge quad) pairs spread evenly over the workgroup's
+//                    lanes; each item evaluates one Philox block per colour,
+//                    which yields the coins of all four edges of the quad.
+//                    Coins are flipped before any neighbour data is read
+//                    ("flip before gather"): `col[e]` and visited[u] are only
+//                    touched for live coins.
+//   discovery        a live coin (u, c) sets bit c of visited[u] with a
+//                    fetch-old atomic OR; only a truly new bit propagates, into
+//                    the next level's frontier mask of u (Listing 1's fusing
+//                    OR).  Marking at discovery means each (vertex, colour)
+//                    enters a frontier exactly once, so the sets equal the
+//                    per-sample reverse BFS of Definition 2 for any schedule.
+//
+// After the last level the batch's RRR sets are extracted (Listing 1's final
+// loop): the touched vertices are sorted (in LDS when few, by a scan of a
+// touched-vertex bitmap otherwise), each colour's members are ranked with
+// wavefront ballots, written to the output pool in ascending order, and the
+// slot's state is reset through the same list.
+#include "bpt.h"
+#include "bpt_internal.hpp"
+#include "bpt_rng.hpp"
+
+namespace bpt {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWaves = kFusedBlock / kWave;
+constexpr int kChunk = kFusedBlock;  // frontier entries staged per pass
+constexpr int kSortCap = 4096;       // touched lists up to this size are sorted in LDS
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+template <int NW>
+struct Stage {  // traversal staging of one chunk of frontier entries
+    uint32_t v[kChunk];
+    uint32_t beg[kChunk];
+    uint32_t end[kChunk];
+    uint32_t thr[kChunk];
+    uint32_t scan[kChunk];
+    unsigned long long mask[kChunk][NW];
+};
+
+template <int NW>
+struct Extract {  // extraction buffers
+    uint32_t sorted[kSortCap];
+    uint32_t wprefix[kWaves][64 * NW];
+};
+
+template <int NW>
+struct FusedShared {
+    union {
+        Stage<NW> st;
+        Extract<NW> ex;
+    } u;
+    unsigned long long coff[64 * NW];  // first pool position of each colour's set
+    uint32_t cnt[64 * NW];             // members per colour
+    uint32_t qlen[2];
+    uint32_t tlen;
+    unsigned long long batch;
+    uint32_t scan_tmp[kWaves];
+    unsigned long long base;
+    unsigned long long stats[kNumStats];
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over the workgroup; *total receives the sum (all threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp, uint32_t* total) {
+    const uint32_t wid = threadIdx.x / kWave;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane_id() == kWave - 1) tmp[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t t = tmp[w];
+        before += (w < (int)wid) ? t : 0u;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        lo |= __shfl_xor(lo, d, kWave);
+        hi |= __shfl_xor(hi, d, kWave);
+    }
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long bcast64(unsigned long long x, int src) {
+    const uint32_t lo = __shfl((uint32_t)x, src, kWave);
+    const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    const uint32_t lane = lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// State of the batch a workgroup is working on.
+template <int NW>
+struct BatchCtx {
+    unsigned long long* visited;  // n * NW
+    unsigned long long* frontier0;  // frontier masks of even levels
+    unsigned long long* frontier1;  // frontier masks of odd levels
+    uint32_t* stamp;
+    uint32_t* queue0;
+    uint32_t* queue1;
+    uint32_t* touched;
+    unsigned long long* tbits;
+    uint32_t n;
+    unsigned int* err;
+};
+
+// (u, c) became reachable: record it once (Listing 1's visited / frontier
+// update, with the visited mark taken at discovery time).
+template <int NW>
+__device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW>& s, uint32_t u, uint32_t c,
+                                         int next, uint32_t tag) {
+    const uint32_t w = c >> 6;
+    const unsigned long long bit = 1ull << (c & 63);
+    const size_t idx = (size_t)u * NW + w;
+    const unsigned long long old = atomicOr(&b.visited[idx], bit);
+    if (old & bit) return;
+    atomicAdd(&s.cnt[c], 1u);
+    unsigned long long* fr = next ? b.frontier1 : b.frontier0;
+    const unsigned long long old_next = atomicOr(&fr[idx], bit);
+    bool push;
+    if constexpr (NW == 1) {
+        push = (old_next == 0);
+    } else {
+        (void)old_next;
+        push = atomicMax(&b.stamp[u], tag) < tag;
+    }
+    if (push) {
+        const uint32_t pos = atomicAdd(&s.qlen[next], 1u);
+        if (pos < b.n) (next ? b.queue1 : b.queue0)[pos] = u;
+        else atomicOr(b.err, (unsigned)kErrQueueOverflow);
+    }
+    const unsigned long long tb = 1ull << (u & 63);
+    const unsigned long long old_t = atomicOr(&b.tbits[u >> 6], tb);
+    if (!(old_t & tb)) {
+        const uint32_t pos = atomicAdd(&s.tlen, 1u);
+        if (pos < b.n) b.touched[pos] = u;
+        else atomicOr(b.err, (unsigned)kErrQueueOverflow);
+    }
+}
+
+// Largest i in [0, cnt) with scan[i] <= t (scan is an exclusive prefix).
+__device__ __forceinline__ uint32_t find_entry(const uint32_t* scan, uint32_t cnt, uint32_t t) {
+    uint32_t lo = 0, hi = cnt;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (scan[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Writes each colour's members (ascending) from the sorted vertex list
+// `list[0..T)` into the pool and clears visited[] for the listed vertices.
+template <int NW>
+__device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW>& s, const uint32_t* list,
+                           uint32_t T, bool write_ok) {
+    const uint32_t lane = lane_id();
+    const uint32_t wid = threadIdx.x / kWave;
+    const uint32_t nchunks = (T + kWave - 1) / kWave;
+    const uint32_t per_wave = (nchunks + kWaves - 1) / kWaves;
+    const uint32_t c_begin = min(nchunks, wid * per_wave);
+    const uint32_t c_end = min(nchunks, c_begin + per_wave);
+
+    // pass 1: per-colour member counts of this wave's chunk range; lane l
+    // keeps the count of colour k*64 + l.
+    uint32_t mycnt[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) mycnt[k] = 0;
+    for (uint32_t ch = c_begin; ch < c_end; ++ch) {
+        const uint32_t idx = ch * kWave + lane;
+        const uint32_t u = idx < T ? list[idx] : kNone;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const unsigned long long mk = (u != kNone) ? b.visited[(size_t)u * NW + k] : 0ull;
+            unsigned long long present = wave_or64(mk);
+            while (present) {
+                const int bpos = __ffsll((long long)present) - 1;
+                present &= present - 1;
+                const unsigned long long bal = __ballot((mk >> bpos) & 1ull);
+                if ((int)lane == bpos) mycnt[k] += (uint32_t)__popcll(bal);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s.u.ex.wprefix[wid][k * 64 + lane] = mycnt[k];
+    __syncthreads();
+    for (uint32_t c = threadIdx.x; c < 64u * NW; c += kFusedBlock) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t t = s.u.ex.wprefix[w][c];
+            s.u.ex.wprefix[w][c] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+
+    // pass 2: write, with lane l holding the next pool position of colour k*64+l
+    unsigned long long run[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) run[k] = s.base + s.coff[k * 64 + lane] + s.u.ex.wprefix[wid][k * 64 + lane];
+    const unsigned long long lt = lanemask_lt();
+    for (uint32_t ch = c_begin; ch < c_end; ++ch) {
+        const uint32_t idx = ch * kWave + lane;
+        const uint32_t u = idx < T ? list[idx] : kNone;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const unsigned long long mk = (u != kNone) ? b.visited[(size_t)u * NW + k] : 0ull;
+            unsigned long long present = wave_or64(mk);
+            while (present) {
+                const int bpos = __ffsll((long long)present) - 1;
+                present &= present - 1;
+                const bool mine = (mk >> bpos) & 1ull;
+                const unsigned long long bal = __ballot(mine);
+                const unsigned long long pos0 = bcast64(run[k], bpos);
+                if (mine && write_ok) pool[pos0 + (unsigned long long)__popcll(bal & lt)] = u;
+                if ((int)lane == bpos) run[k] += (unsigned long long)__popcll(bal);
+            }
+        }
+        if (u != kNone) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) b.visited[(size_t)u * NW + k] = 0ull;
+        }
+    }
+}
+
+template <int NW>
+__global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
+    __shared__ FusedShared<NW> s;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n = a.g.n;
+    const uint32_t slot = blockIdx.x;
+    constexpr uint32_t C = 64u * NW;
+
+    BatchCtx<NW> b;
+    b.n = n;
+    b.err = &a.ctl->err;
+    b.visited = a.ws.visited + (size_t)slot * n * NW;
+    b.frontier0 = a.ws.frontier + (size_t)slot * 2 * n * NW;
+    b.frontier1 = b.frontier0 + (size_t)n * NW;
+    b.stamp = (NW > 1) ? a.ws.stamp + (size_t)slot * n : nullptr;
+    b.queue0 = a.ws.queue + (size_t)slot * 2 * n;
+    b.queue1 = b.queue0 + n;
+    b.touched = a.ws.touched + (size_t)slot * n;
+    b.tbits = a.ws.tbits + (size_t)slot * bitmap_words(n);
+
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t layout = a.g.prob_layout;
+
+    if (tid < kNumStats) s.stats[tid] = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s.batch = atomicAdd(&a.ctl->work_counter, 1ull);
+        __syncthreads();
+        const uint64_t batch = s.batch;
+        if (batch >= a.n_batches) break;
+        const uint64_t s0 = a.first_sample + batch * C;
+        const uint32_t ncol = (uint32_t)min((uint64_t)C, a.n_samples - batch * C);
+
+        uint32_t base_tag = 0;
+        if constexpr (NW > 1) {
+            base_tag = a.ws.slot_tag[slot] + 1;
+            if (base_tag > 0xFFFFFFFFu - n - 8u) {  // tags would wrap: restart them
+                for (uint32_t v = tid; v < n; v += kFusedBlock) b.stamp[v] = 0;
+                __threadfence();
+                __syncthreads();
+                base_tag = 1;
+            }
+        }
+        for (uint32_t c = tid; c < C; c += kFusedBlock) s.cnt[c] = 0;
+        if (tid == 0) {
+            s.qlen[0] = 0;
+            s.qlen[1] = 0;
+            s.tlen = 0;
+        }
+        __syncthreads();
+
+        // Frontier initialisation: colour c starts at its sample's start vertex.
+        for (uint32_t c = tid; c < ncol; c += kFusedBlock)
+            discover<NW>(b, s, start_of(s0 + c, n, k0, k1), c, 0, base_tag);
+
+        // Level-synchronous fused traversal.
+        uint32_t level = 0;
+        unsigned long long th_entries = 0, th_ea = 0, th_te = 0, th_philox = 0, th_live = 0, th_members = 0;
+        for (;;) {
+            __syncthreads();
+            const int cur = level & 1, nxt = cur ^ 1;
+            const uint32_t F = min(s.qlen[cur], n);
+            if (F == 0) break;
+            if (level > n) {
+                if (tid == 0) atomicOr(&a.ctl->err, (unsigned)kErrLevelBound);
+                break;
+            }
+            __syncthreads();
+            if (tid == 0) s.qlen[nxt] = 0;
+            const uint32_t tag = base_tag + level + 1;
+
+            for (uint32_t c0 = 0; c0 < F; c0 += kChunk) {
+                const uint32_t cnt = min((uint32_t)kChunk, F - c0);
+                uint32_t items = 0;
+                if (tid < cnt) {
+                    const uint32_t v = (cur ? b.queue1 : b.queue0)[c0 + tid];
+                    const uint32_t beg = a.g.rowptr[v], end = a.g.rowptr[v + 1];
+                    uint32_t pc = 0;
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) {
+                        const unsigned long long mk =
+                            atomicExch(&(cur ? b.frontier1 : b.frontier0)[(size_t)v * NW + k], 0ull);
+                        s.u.st.mask[tid][k] = mk;
+                        pc += (uint32_t)__popcll(mk);
+                    }
+                    uint32_t thr = 0;
+                    if (layout == BPT_PROB_ROW) thr = a.g.thr_row[v];
+                    else if (layout == BPT_PROB_UNIFORM) thr = a.g.thr_uniform;
+                    const uint32_t deg = end - beg;
+                    const bool never = (layout != BPT_PROB_EDGE) && thr == 0;
+                    items = (deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
+                    s.u.st.v[tid] = v;
+                    s.u.st.beg[tid] = beg;
+                    s.u.st.end[tid] = end;
+                    s.u.st.thr[tid] = thr;
+                    th_entries += 1;
+                    th_ea += deg;
+                    th_te += (unsigned long long)pc * deg;
+                    th_members += pc;
+                }
+                uint32_t total;
+                const uint32_t excl = block_excl_scan(items, s.scan_tmp, &total);
+                if (tid < cnt) s.u.st.scan[tid] = excl;
+                __syncthreads();
+
+                for (uint32_t t = tid; t < total; t += kFusedBlock) {
+                    const uint32_t i = find_entry(s.u.st.scan, cnt, t);
+                    const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
+                    const uint32_t quad = (beg >> 2) + (t - s.u.st.scan[i]);
+                    const uint32_t e0 = quad << 2;
+                    uint32_t t0, t1, t2, t3;
+                    if (layout == BPT_PROB_EDGE) {
+                        const uint4 tt = *reinterpret_cast<const uint4*>(a.g.thr_edge + e0);
+                        t0 = tt.x; t1 = tt.y; t2 = tt.z; t3 = tt.w;
+                    } else {
+                        t0 = t1 = t2 = t3 = s.u.st.thr[i];
+                    }
+                    // words of this quad that belong to the row
+                    uint32_t valid = 0xFu;
+                    if (e0 < beg) valid &= 0xFu << (beg - e0);
+                    if (end - e0 < 4) valid &= (1u << (end - e0)) - 1u;
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) {
+                        unsigned long long mk = s.u.st.mask[i][k];
+                        while (mk) {
+                            const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
+                            mk &= mk - 1;
+                            const uint32_t c = (uint32_t)k * 64u + bpos;
+                            const Block4 r = coin_block(quad, s0 + c, k0, k1);
+                            ++th_philox;
+                            uint32_t live = (coin_live(r.w0, t0) ? 1u : 0u) | (coin_live(r.w1, t1) ? 2u : 0u) |
+                                            (coin_live(r.w2, t2) ? 4u : 0u) | (coin_live(r.w3, t3) ? 8u : 0u);
+                            live &= valid;
+                            while (live) {
+                                const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
+                                live &= live - 1;
+                                ++th_live;
+                                discover<NW>(b, s, a.g.col[e0 + j], c, nxt, tag);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            ++level;
+        }
+
+        // ---- RRR set extraction (Listing 1's final loop) ----
+        __threadfence();  // atomics above completed in L2; drop stale L1 lines
+        __syncthreads();
+        const uint32_t T = min(s.tlen, n);
+        if (tid == 0) {
+            unsigned long long run = 0;
+            for (uint32_t c = 0; c < C; ++c) {
+                s.coff[c] = run;
+                run += s.cnt[c];
+            }
+            s.base = atomicAdd(&a.ctl->pool_cursor, run);
+            if (s.base + run > a.out.pool_cap) atomicOr(&a.ctl->err, (unsigned)kErrPoolOverflow);
+            if constexpr (NW > 1) a.ws.slot_tag[slot] = base_tag + level + 1;
+            atomicAdd(&s.stats[kStatLevels], (unsigned long long)level);
+            atomicMax(&s.stats[kStatMaxLevels], (unsigned long long)level);
+            atomicAdd(&s.stats[kStatBatches], 1ull);
+        }
+        __syncthreads();
+        const bool write_ok = s.base + s.coff[C - 1] + s.cnt[C - 1] <= a.out.pool_cap;
+        for (uint32_t c = tid; c < ncol; c += kFusedBlock) {
+            a.out.counts[s0 - a.first_sample + c] = s.cnt[c];
+            a.out.where[s0 - a.first_sample + c] = s.base + s.coff[c];
+        }
+
+        const uint32_t* list;
+        if (T <= (uint32_t)kSortCap) {
+            uint32_t P = 64;
+            while (P < T) P <<= 1;
+            for (uint32_t i = tid; i < P; i += kFusedBlock) s.u.ex.sorted[i] = i < T ? b.touched[i] : kNone;
+            __syncthreads();
+            for (uint32_t k = 2; k <= P; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = tid; i < P; i += kFusedBlock) {
+                        const uint32_t ixj = i ^ j;
+                        if (ixj > i) {
+                            const uint32_t x = s.u.ex.sorted[i], y = s.u.ex.sorted[ixj];
+                            const bool up = (i & k) == 0;
+                            if ((x > y) == up) {
+                                s.u.ex.sorted[i] = y;
+                                s.u.ex.sorted[ixj] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t i = tid; i < T; i += kFusedBlock) b.tbits[s.u.ex.sorted[i] >> 6] = 0ull;
+            list = s.u.ex.sorted;
+        } else {
+            // touched-vertex bitmap, scanned in vertex order, gives the sorted list
+            const size_t words = bitmap_words(n);
+            const size_t per_t = (words + kFusedBlock - 1) / kFusedBlock;
+            const size_t w0 = min(words, (size_t)tid * per_t), w1 = min(words, w0 + per_t);
+            uint32_t ones = 0;
+            for (size_t w = w0; w < w1; ++w) ones += (uint32_t)__popcll(b.tbits[w]);
+            uint32_t all;
+            uint32_t pos = block_excl_scan(ones, s.scan_tmp, &all);
+            for (size_t w = w0; w < w1; ++w) {
+                unsigned long long x = b.tbits[w];
+                if (!x) continue;
+                b.tbits[w] = 0ull;
+                while (x) {
+                    const uint32_t bpos = (uint32_t)(__ffsll((long long)x) - 1);
+                    x &= x - 1;
+                    if (pos < n) b.touched[pos] = (uint32_t)(w * 64 + bpos);
+                    ++pos;
+                }
+            }
+            __syncthreads();
+            list = b.touched;
+        }
+        __syncthreads();
+        write_sets<NW>(a.out.pool, b, s, list, T, write_ok);
+        // thread-local counters into the workgroup's totals
+        atomicAdd(&s.stats[kStatEntries], th_entries);
+        atomicAdd(&s.stats[kStatEdgeAccesses], th_ea);
+        atomicAdd(&s.stats[kStatSampleEdges], th_te);
+        atomicAdd(&s.stats[kStatPhilox], th_philox);
+        atomicAdd(&s.stats[kStatLive], th_live);
+        atomicAdd(&s.stats[kStatMembers], th_members);
+        __threadfence();  // resets reach L2 before the next batch's atomics
+    }
+    __syncthreads();
+    if (tid < kNumStats) {
+        if (tid == kStatMaxLevels) atomicMax(&a.ctl->stats[tid], s.stats[tid]);
+        else atomicAdd(&a.ctl->stats[tid], s.stats[tid]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fused(const FusedArgs& a, int nw, int grid, hipStream_t stream) {
+    switch (nw) {
+        case 1: hipLaunchKernelGGL(fused_bpt_kernel<1>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL(fused_bpt_kernel<2>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
+        case 4: hipLaunchKernelGGL(fused_bpt_kernel<4>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
+        case 8: hipLaunchKernelGGL(fused_bpt_kernel<8>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
+        case 16: hipLaunchKernelGGL(fused_bpt_kernel<16>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bpt

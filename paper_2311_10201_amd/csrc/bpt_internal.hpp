@@ -1,0 +1,119 @@
+// Internal types shared by the host driver and the kernels of libbpt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bpt {
+
+// ---------------------------------------------------------------------------
+// Device graph store: transposed CSR (row v = sources of v's in-edges, in
+// ascending order; position in `col` = canonical edge id) plus thresholds.
+// ---------------------------------------------------------------------------
+struct DevGraph {
+    const uint32_t* rowptr;    // n+1
+    const uint32_t* col;       // m (padded to a multiple of 4)
+    const uint32_t* thr_row;   // n, BPT_PROB_ROW layout only
+    const uint32_t* thr_edge;  // m padded to a multiple of 4 with 0, BPT_PROB_EDGE only
+    uint32_t thr_uniform;      // BPT_PROB_UNIFORM layout only
+    uint32_t prob_layout;      // BPT_PROB_*
+    uint32_t n;
+    uint32_t m;
+};
+
+// Counters accumulated by the kernels (device copy: unsigned long long[kNumStats]).
+enum StatIndex {
+    kStatMembers = 0,
+    kStatSampleEdges,
+    kStatEdgeAccesses,
+    kStatEntries,
+    kStatPhilox,
+    kStatLive,
+    kStatLevels,
+    kStatMaxLevels,
+    kStatBatches,
+    kNumStats
+};
+
+// Device-side error bits (unsigned int).
+enum ErrorBits : unsigned int {
+    kErrPoolOverflow = 1u,   // output pool too small: grow and run again
+    kErrQueueOverflow = 2u,  // frontier queue exceeded n entries (cannot happen)
+    kErrLevelBound = 4u,     // more than n+1 levels in one batch (cannot happen)
+};
+
+// Small per-call control block in device memory.
+struct Control {
+    unsigned long long pool_cursor;  // output entries claimed so far
+    unsigned long long total;        // offsets[n_samples] after the scan
+    unsigned long long work_counter; // next batch / sample to claim
+    unsigned int err;                // ErrorBits
+    unsigned int pad_;
+    unsigned long long stats[kNumStats];
+};
+
+// Per-slot state of the fused traversal (one slot per resident workgroup).
+// All arrays are zero between batches except `stamp`, whose values only grow.
+struct FusedSlots {
+    unsigned long long* visited;   // slots * n * NW
+    unsigned long long* frontier;  // slots * 2 * n * NW (two levels in flight)
+    uint32_t* stamp;               // slots * n           (NW > 1 only)
+    uint32_t* queue;               // slots * 2 * n
+    uint32_t* touched;             // slots * n
+    unsigned long long* tbits;     // slots * words(n)
+    uint32_t* slot_tag;            // slots
+    uint32_t slots;
+};
+
+struct Output {
+    uint32_t* counts;           // n_samples: |R_s|
+    unsigned long long* where;  // n_samples: position of R_s in `pool`
+    uint32_t* pool;             // members, set by set, in claim order
+    unsigned long long pool_cap;
+};
+
+struct FusedArgs {
+    DevGraph g;
+    FusedSlots ws;
+    Output out;
+    Control* ctl;
+    uint64_t seed;
+    uint64_t first_sample;
+    uint64_t n_samples;
+    uint64_t n_batches;
+    uint32_t colors;
+};
+
+// Per-wave state of the unfused traversal.
+struct UnfusedSlots {
+    unsigned long long* vbits;  // slots * words(n): visited bitmap
+    uint32_t* log;              // slots * n: visit order (level by level)
+    uint32_t slots;
+};
+
+struct UnfusedArgs {
+    DevGraph g;
+    UnfusedSlots ws;
+    Output out;
+    Control* ctl;
+    uint64_t seed;
+    uint64_t first_sample;
+    uint64_t n_samples;
+};
+
+__host__ __device__ inline size_t bitmap_words(uint32_t n) { return ((size_t)n + 63) / 64; }
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_fused(const FusedArgs& a, int nw, int grid, hipStream_t stream);
+hipError_t launch_unfused(const UnfusedArgs& a, int grid, hipStream_t stream);
+hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
+                           uint64_t n_samples, unsigned long long* offsets, uint32_t* vertices,
+                           unsigned long long capacity, Control* ctl, void* scratch, size_t scratch_bytes,
+                           hipStream_t stream);
+size_t finalize_scratch_bytes(uint64_t n_samples);
+
+constexpr int kFusedBlock = 256;    // threads per fused workgroup
+constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
+
+}  // namespace bpt

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path (through the C ABI) returns exactly the oracle's
+RRR sets, for every colour count, the unfused path, every probability layout
+and the degenerate cases; its work counters match the oracle's accounting of
+Sections 3.1-3.2."""
+
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_2311_10201_amd as bpt
+from gpu_util import announce, assert_same_sets, sample_device
+
+pytestmark = pytest.mark.gpu
+
+COLORS = [64, 128, 256, 512, 1024]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "er1000_m10000_p0.1_seed42.txt")
+
+
+@pytest.fixture(scope="module")
+def er_case():
+    n, m = 1000, 10_000
+    src, dst = graphgen.er_graph(n, m, seed=42)
+    prob = graphgen.uniform_prob(m, 0.1)
+    return n, src, dst, prob
+
+
+def test_er_host_api_matches_oracle_and_golden(er_case):
+    announce("ER n=1000 m=10000 p=0.1 S=64 C=64 host API")
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    assert bpt.bpt_graph_info(g) == (n, 10_000, bpt.BPT_PROB_UNIFORM)
+    res = bpt.bpt_sample_rrr(g, 64, 64, 42)
+    ref = oracle.Graph(n, src, dst, prob).sample(42, 64)
+    assert_same_sets(res.offsets, res.vertices, ref, "host API")
+    with open(GOLDEN) as f:
+        rows = [line.split() for line in f if not line.startswith("#")]
+    for i, row in enumerate(rows):
+        assert res.set_of(i).tolist() == [int(x) for x in row[1:]]
+
+
+def test_er_all_colors_and_unfused(er_case):
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    og = oracle.Graph(n, src, dst, prob)
+    S = 3000  # ragged: not a multiple of any colour count
+    ref = og.sample(42, S, nthreads=8)
+    te = int(ref.te.sum())
+    for c in COLORS:
+        announce(f"ER S={S} C={c}")
+        off, ver, cnt = sample_device(g, 0, S, c, 42)
+        assert_same_sets(off, ver, ref, f"fused C={c}")
+        assert cnt.sample_edges == te
+        assert cnt.members == int(ref.offsets[-1])
+        assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+        assert cnt.frontier_entries == oracle.fused_frontier_entries(ref, c)
+        assert cnt.batches == (S + c - 1) // c
+    announce(f"ER S={S} unfused")
+    off, ver, cnt = sample_device(g, 0, S, 0, 42, flags=bpt.BPT_FLAG_UNFUSED)
+    assert_same_sets(off, ver, ref, "unfused")
+    assert cnt.edge_accesses == te and cnt.sample_edges == te
+
+
+@pytest.mark.parametrize("layout", ["uniform", "row", "edge"])
+def test_probability_layouts(layout):
+    n = 3000
+    src, dst = graphgen.rmat_graph(12, 8, 0.57, 0.19, 0.19, seed=5)
+    src = src % n
+    dst = dst % n
+    key = np.unique((src.astype(np.uint64) << np.uint64(32)) | dst)
+    src = (key >> np.uint64(32)).astype(np.uint32)
+    dst = (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    if layout == "uniform":
+        prob = graphgen.uniform_prob(len(src), 0.07)
+        want = bpt.BPT_PROB_UNIFORM
+    elif layout == "row":
+        prob = graphgen.wc_prob(n, dst)
+        want = bpt.BPT_PROB_ROW
+    else:
+        prob = (np.random.Generator(np.random.PCG64(3)).random(len(src), dtype=np.float32)
+                * np.float32(0.3)).astype(np.float32)
+        want = bpt.BPT_PROB_EDGE
+    announce(f"layout {layout} n={n} m={len(src)}")
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    assert bpt.bpt_graph_info(g)[2] == want
+    og = oracle.Graph(n, src, dst, prob)
+    S = 2500
+    ref = og.sample(7, S, nthreads=8)
+    for c in (64, 256):
+        off, ver, cnt = sample_device(g, 0, S, c, 7)
+        assert_same_sets(off, ver, ref, f"{layout} C={c}")
+        assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+    off, ver, _ = sample_device(g, 0, S, 0, 7, flags=bpt.BPT_FLAG_UNFUSED)
+    assert_same_sets(off, ver, ref, f"{layout} unfused")
+
+
+def test_degenerate_probabilities():
+    src, dst = graphgen.rmat_graph(11, 8, 0.57, 0.19, 0.19, seed=9)
+    n = 1 << 11
+    for p in (0.0, 1.0):
+        announce(f"p={p}")
+        prob = graphgen.uniform_prob(len(src), p)
+        g = bpt.bpt_create_graph(n, src, dst, prob)
+        ref = oracle.Graph(n, src, dst, prob).sample(3, 700, nthreads=8)
+        for c, flags in ((64, 0), (1024, 0), (0, bpt.BPT_FLAG_UNFUSED)):
+            off, ver, _ = sample_device(g, 0, 700, c, 3, flags=flags)
+            assert_same_sets(off, ver, ref, f"p={p} C={c} flags={flags}")
+        if p == 0.0:
+            assert np.all(np.diff(ref.offsets) == 1)
+
+
+def test_edge_cases_small():
+    # no edges at all
+    announce("m=0")
+    g = bpt.bpt_create_graph(17, [], [], [])
+    off, ver, _ = sample_device(g, 0, 100, 64, 1)
+    assert np.array_equal(np.diff(off), np.ones(100, dtype=np.uint64))
+    ref = oracle.Graph(17, np.array([], np.uint32), np.array([], np.uint32), np.array([], np.float32)).sample(1, 100)
+    assert_same_sets(off, ver, ref, "m=0")
+    # zero samples
+    announce("S=0")
+    off, ver, cnt = sample_device(g, 0, 0, 64, 1)
+    assert off.tolist() == [0] and len(ver) == 0 and cnt.samples == 0
+    res = bpt.bpt_sample_rrr(g, 0, 64, 1)
+    assert res.offsets.tolist() == [0]
+    # single vertex with a self-loop, one sample
+    announce("n=1 self-loop")
+    g1 = bpt.bpt_create_graph(1, [0], [0], [1.0])
+    off, ver, _ = sample_device(g1, 0, 1, 64, 5)
+    assert off.tolist() == [0, 1] and ver.tolist() == [0]
+
+
+def test_self_loops_and_sample_ranges():
+    n = 500
+    src, dst, prob = graphgen.random_small_graph(n, 4000, 77, allow_self_loops=True)
+    assert np.any(src == dst)
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    og = oracle.Graph(n, src, dst, prob)
+    seed = (1 << 63) + 12345  # high key word in use
+    first = (1 << 32) - 300   # ids cross 2^32
+    ref = og.sample(seed, 1000, first_sample=first, nthreads=8)
+    announce("ranges crossing 2^32")
+    off, ver, _ = sample_device(g, first, 1000, 128, seed)
+    assert_same_sets(off, ver, ref, "first_sample")
+    # two shards concatenate to the whole
+    o1, v1, _ = sample_device(g, first, 333, 64, seed)
+    o2, v2, _ = sample_device(g, first + 333, 667, 512, seed)
+    assert np.array_equal(np.concatenate([v1, v2]), ref.members)
+    assert np.array_equal(np.concatenate([o1[:-1], o2 + o1[-1]]), ref.offsets)
+
+
+def test_erange_and_repeatability(er_case):
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    import torch
+    S = 500
+    off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    vert = torch.empty(8, dtype=torch.int32, device="cuda")
+    announce("ERANGE")
+    st, total, _ = bpt.bpt_sample_rrr_device(g, 0, S, 64, 9, 0, None, off, vert, 8)
+    assert st == bpt.BPT_ERANGE and total > 8
+    a = sample_device(g, 0, S, 64, 9)
+    for _ in range(3):
+        b = sample_device(g, 0, S, 64, 9)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_invalid_sampling_arguments(er_case):
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    for c in (1, 32, 96, 2048):
+        with pytest.raises(bpt.BptError) as ei:
+            bpt.bpt_sample_rrr(g, 10, c, 1)
+        assert ei.value.status == bpt.BPT_EINVAL
+    with pytest.raises(bpt.BptError):
+        bpt.bpt_sample_rrr(g, 1 << 34, 64, 1)
