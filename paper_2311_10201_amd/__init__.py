@@ -86,7 +86,13 @@ def load_library():
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
                            "`python -m paper_2311_10201_amd.build` (there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime.  Loading torch first lets libbpt's
+    # dependency on libamdhip64.so.7 bind to that same runtime, so device
+    # buffers and streams from torch are valid inside libbpt; two runtimes in
+    # one process would each try to own the GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(_LIB_PATH)
+    _check_single_hip_runtime()
     u32, u64, i32, vp, cp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p
     sig = {
         "bpt_create_graph": (vp, [u32, u64, vp, vp, vp]),
@@ -113,6 +119,16 @@ def load_library():
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def _check_single_hip_runtime():
+    try:
+        with open("/proc/self/maps") as f:
+            paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    except OSError:
+        return
+    if len(paths) > 1:
+        raise RuntimeError(f"two HIP runtimes are loaded in this process: {sorted(paths)}")
 
 
 def _raise_last():
