@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""RRR-set sampling throughput on one MI355X: fused BPTs vs the unfused traversal.
+
+    python bench.py [--steps K] [--warmup W] [--workload rmat20-wc] [--gpus 1]
+
+One "step" samples the whole workload once (all its RRR sets) with the fused
+traversal at the chosen colour count; inputs are resident in HBM and the sets
+are written to device memory.  Prints one JSON line: samples/s (the value),
+traversed edges/s, the unfused and other colour-count rates on the same GPU,
+the traversal kernel's roofline, and the CPU oracle timed on the host cores
+(whose output is also compared with the GPU's, set by set).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("RRR samples/sec and traversed edges/sec (fused vs unfused, bit-exact); % HBM peak")
+
+WORKLOADS = {
+    # R-MAT scale 20, edge factor 16, weighted cascade, 100,000 samples
+    "rmat20-wc": dict(kind="rmat", scale=20, ef=16, a=0.57, b=0.19, c=0.19, graph_seed=20, prob="wc",
+                      samples=100_000, seed=42, colors=(64, 256)),
+    # R-MAT scale 22, edge factor 16, uniform p = 0.01, 1,000,000 samples
+    "rmat22-p0.01": dict(kind="rmat", scale=22, ef=16, a=0.57, b=0.19, c=0.19, graph_seed=22, prob=0.01,
+                         samples=1_000_000, seed=42, colors=(64, 128, 256)),
+    # Erdos-Renyi n = 1,000, m = 10,000, p = 0.1, 64 samples
+    "er1000-p0.1": dict(kind="er", n=1000, m=10_000, graph_seed=42, prob=0.1, samples=64, seed=42, colors=(64,)),
+}
+
+# ALU roofline of one Philox4x32-10 block on gfx950, from the instruction mix
+# the compiler emits for a block (40 v_mul_hi/lo_u32 at a quarter of the full
+# issue rate, 40 v_xor_b32, 8 compare/select at full rate) and the chip's
+# vector issue rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s).
+LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+SLOTS_PER_BLOCK = 40 * 4 + 40 + 8
+PEAK_PHILOX_BLOCKS = LANE_SLOTS_PER_S / SLOTS_PER_BLOCK
+
+KERNEL_SOURCES = ["paper_2311_10201_amd/csrc/bpt_fused.hip", "paper_2311_10201_amd/csrc/bpt_rng.hpp",
+                  "paper_2311_10201_amd/csrc/bpt_internal.hpp"]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_graph(w):
+    import graphgen
+    import numpy as np
+    if w["kind"] == "rmat":
+        src, dst = graphgen.rmat_graph(w["scale"], w["ef"], w["a"], w["b"], w["c"], seed=w["graph_seed"])
+        n = 1 << w["scale"]
+    else:
+        n = w["n"]
+        src, dst = graphgen.er_graph(n, w["m"], seed=w["graph_seed"])
+    if w["prob"] == "wc":
+        prob = graphgen.wc_prob(n, dst)
+    else:
+        prob = graphgen.uniform_prob(len(src), w["prob"])
+    return n, src, dst, prob.astype(np.float32)
+
+
+def measured_traffic(workload: str, colors: int):
+    """HBM bytes per traversal launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    e = rec.get(f"{workload}/C{colors}")
+    if not e or e.get("kernel_digest") != kernel_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat20-wc", choices=sorted(WORKLOADS))
+    ap.add_argument("--colors", type=int, default=0, help="0: pick the fastest listed colour count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sampling shards by sample-id range; see the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2311_10201_amd as bpt
+
+    w = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    log(f"workload {args.workload}: generating graph")
+    n, src, dst, prob = make_graph(w)
+    m = len(src)
+    S, seed = w["samples"], w["seed"]
+    t0 = time.perf_counter()
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    log(f"graph n={n} m={m} layout={bpt.bpt_graph_info(g)[2]} built in {time.perf_counter() - t0:.2f}s")
+    stream = torch.cuda.current_stream()
+    off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    cap = max(1 << 20, 48 * S)
+    vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+
+    def step(colors, flags=0):
+        nonlocal vert, cap
+        st, total, cnt = bpt.bpt_sample_rrr_device(g, 0, S, colors, seed, flags, stream, off, vert, cap)
+        if st == bpt.BPT_ERANGE:
+            cap = total + total // 8
+            vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+            st, total, cnt = bpt.bpt_sample_rrr_device(g, 0, S, colors, seed, flags, stream, off, vert, cap)
+        assert st == bpt.BPT_OK
+        return total, cnt
+
+    def timed(colors, flags, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cnts = [step(colors, flags)[1] for _ in range(steps)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, cnts
+
+    variants = [(c, 0) for c in w["colors"]] + [(0, bpt.BPT_FLAG_UNFUSED)]
+    warm = {}
+    for c, fl in variants:
+        name = "unfused" if fl else f"fused{c}"
+        for i in range(max(1, args.warmup)):
+            t = time.perf_counter()
+            total, cnt = step(c, fl)
+            torch.cuda.synchronize()
+            warm[name] = time.perf_counter() - t
+        log(f"warmup {name}: {warm[name] * 1e3:.2f} ms, members={total}")
+
+    colors = args.colors or min(w["colors"], key=lambda c: warm[f"fused{c}"])
+    log(f"timing fused C={colors}: {args.steps} steps")
+    sec, cnts = timed(colors, 0, args.steps)
+    cnt = cnts[-1]
+    value = S / sec
+    te_per_s = cnt.sample_edges / sec
+    trav_s = sum(c.traversal_ns for c in cnts) / len(cnts) / 1e9
+    blocks = cnt.philox_blocks
+    # keep the headline output for the parity check
+    total = int(off[-1].item())
+    gpu_off = off.cpu().numpy().view(np.uint64).copy()
+    gpu_ver = vert[:total].cpu().numpy().view(np.uint32).copy()
+
+    others = {}
+    for c, fl in variants:
+        name = "unfused" if fl else f"fused{c}"
+        if not fl and c == colors:
+            others[name] = dict(samples_per_s=value, ms_per_step=sec * 1e3,
+                                traversal_ms=trav_s * 1e3, edge_accesses=cnt.edge_accesses)
+            continue
+        s2, c2 = timed(c, fl, args.steps)
+        others[name] = dict(samples_per_s=S / s2, ms_per_step=s2 * 1e3,
+                            traversal_ms=sum(x.traversal_ns for x in c2) / len(c2) / 1e6,
+                            edge_accesses=c2[-1].edge_accesses)
+        log(f"{name}: {s2 * 1e3:.2f} ms/step")
+
+    achieved = blocks / trav_s
+    traffic = measured_traffic(args.workload, colors)
+    roofline = {
+        "bound": "alu",
+        "kernel": f"fused_bpt_kernel<{colors // 64}>",
+        "achieved": achieved / 1e9,
+        "peak": PEAK_PHILOX_BLOCKS / 1e9,
+        "unit": "G Philox4x32-10 blocks/s",
+        "frac": achieved / PEAK_PHILOX_BLOCKS,
+        "traffic": traffic,
+        "per_launch": {"philox_blocks": blocks, "traversal_ms": trav_s * 1e3,
+                       "kernel_digest": kernel_digest()},
+    }
+    hbm_bytes = None
+    if traffic:
+        hbm_bytes = traffic / trav_s
+        roofline["hbm_GBps"] = hbm_bytes / 1e9
+        roofline["hbm_frac_of_8TBps"] = hbm_bytes / 8e12
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "graph": (f"R-MAT scale {w['scale']}, edge factor {w['ef']}, a={w['a']} b={w['b']} c={w['c']}, "
+                      "self-loops and duplicates dropped" if w["kind"] == "rmat"
+                      else f"Erdos-Renyi n={w['n']} m={w['m']}"),
+            "prob": "weighted cascade 1/indeg(v)" if w["prob"] == "wc" else f"uniform {w['prob']}",
+            "n": n, "m": m, "samples": S, "colors": colors, "seed": seed,
+        },
+        "edges_per_s": te_per_s,
+        "sample_edges": cnt.sample_edges,
+        "edge_accesses": cnt.edge_accesses,
+        "fusion_ratio_te_over_ea": cnt.sample_edges / max(1, cnt.edge_accesses),
+        "members": cnt.members,
+        "max_levels": cnt.max_levels,
+        "fused_vs_unfused": value / others["unfused"]["samples_per_s"],
+        "variants": others,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        og = oracle.Graph(n, src, dst, prob)
+        t = time.perf_counter()
+        ref = og.sample(seed, S, nthreads=threads)
+        cpu_s = time.perf_counter() - t
+        same = bool(np.array_equal(ref.offsets, gpu_off) and np.array_equal(ref.members, gpu_ver))
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
+        result["cpu_baseline"] = {
+            "value": S / cpu_s, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {S} samples of the workload (one reverse BFS per sample), {cpu_model}",
+            "edges_per_s": float(ref.te.sum()) / cpu_s,
+        }
+        result["parity"] = f"bit-exact vs oracle on all {S} sets" if same else "MISMATCH vs oracle"
+        log(f"cpu oracle: {cpu_s:.2f}s on {threads} threads; parity {'ok' if same else 'FAILED'}")
+        if not same:
+            print(json.dumps(result), flush=True)
+            return 1
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -74,28 +74,33 @@ def rmat_graph(scale: int, edge_factor: int, a: float, b: float, c: float,
 
     Each draw picks, bit by bit from the most significant, one quadrant of the
     adjacency matrix: (src bit, dst bit) = (0,0) with probability a, (0,1)
-    with b, (1,0) with c and (1,1) with d = 1-a-b-c.  No noise, no
-    relabelling.  Self-loops and duplicate (src, dst) pairs are dropped; the
-    surviving edges are returned sorted by (src, dst) as uint32 arrays.
+    with b, (1,0) with c and (1,1) with d = 1-a-b-c (a uniform 32-bit draw per
+    bit, compared with the cumulative thresholds).  No noise, no relabelling.
+    Self-loops and duplicate (src, dst) pairs are dropped; the surviving edges
+    are returned sorted by (src, dst) as uint32 arrays.
     """
     n_draw = edge_factor << scale
     rng = np.random.Generator(np.random.PCG64(seed))
-    src = np.zeros(n_draw, dtype=np.uint32)
-    dst = np.zeros(n_draw, dtype=np.uint32)
-    t_ab = a + b
-    t_abc = a + b + c
-    for level in range(scale):
-        bit = np.uint32(1 << (scale - 1 - level))
-        r = rng.random(n_draw, dtype=np.float64)
-        src_bit = r >= t_ab                      # quadrants c, d
-        dst_bit = ((r >= a) & (r < t_ab)) | (r >= t_abc)   # quadrants b, d
-        src |= np.where(src_bit, bit, np.uint32(0))
-        dst |= np.where(dst_bit, bit, np.uint32(0))
-        del r, src_bit, dst_bit
-    keep = src != dst
-    key = (src[keep].astype(np.uint64) << np.uint64(32)) | dst[keep].astype(np.uint64)
-    del src, dst, keep
-    key = np.unique(key)
+    t_a = np.uint32(min(int(round(a * 2**32)), 2**32 - 1))
+    t_ab = np.uint32(min(int(round((a + b) * 2**32)), 2**32 - 1))
+    t_abc = np.uint32(min(int(round((a + b + c) * 2**32)), 2**32 - 1))
+    keys = []
+    chunk = 1 << 20
+    for lo in range(0, n_draw, chunk):
+        k = min(chunk, n_draw - lo)
+        src = np.zeros(k, dtype=np.uint32)
+        dst = np.zeros(k, dtype=np.uint32)
+        for level in range(scale):
+            bit = np.uint32(1 << (scale - 1 - level))
+            r = rng.integers(0, 2**32, size=k, dtype=np.uint32)
+            src_bit = r >= t_ab                                # quadrants c, d
+            dst_bit = ((r >= t_a) & (r < t_ab)) | (r >= t_abc)  # quadrants b, d
+            src |= src_bit.astype(np.uint32) * bit
+            dst |= dst_bit.astype(np.uint32) * bit
+        keep = src != dst
+        keys.append((src[keep].astype(np.uint64) << np.uint64(32)) | dst[keep].astype(np.uint64))
+    key = np.unique(np.concatenate(keys))
+    del keys
     out_src = (key >> np.uint64(32)).astype(np.uint32)
     out_dst = (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)
     return out_src, out_dst

@@ -84,6 +84,9 @@ typedef struct bpt_counters {
     uint64_t levels;           /* sum over batches of BFS levels                        */
     uint64_t max_levels;       /* deepest batch                                         */
     uint64_t batches;          /* batches (fused) or traversals (unfused) run           */
+    uint64_t traversal_ns;     /* duration of the traversal kernel (HIP events on the
+                                  call's stream), nanoseconds                           */
+    uint64_t finalize_ns;      /* duration of the CSR assembly kernels, nanoseconds     */
 } bpt_counters;
 
 /* ------------------------------------------------------------------------

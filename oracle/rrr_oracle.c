@@ -136,20 +136,21 @@ typedef struct or_graph {
     uint32_t* in_thr;   /* threshold of canonical edge e */
 } or_graph;
 
-typedef struct edge_rec {
-    uint32_t src, dst;
-    float prob;
-} edge_rec;
-
-static int cmp_dst_src(const void* a, const void* b)
+/* Stable counting sort of the edge indices in `in` by key[] (values < n),
+ * written to `out`. */
+static int counting_sort(const uint32_t* key, uint32_t n, uint64_t m, const uint64_t* in, uint64_t* out)
 {
-    const edge_rec* x = (const edge_rec*)a;
-    const edge_rec* y = (const edge_rec*)b;
-    if (x->dst != y->dst)
-        return x->dst < y->dst ? -1 : 1;
-    if (x->src != y->src)
-        return x->src < y->src ? -1 : 1;
-    return 0;
+    uint64_t* start = (uint64_t*)calloc((size_t)n + 1, sizeof(uint64_t));
+    if (!start)
+        return OR_ENOMEM;
+    for (uint64_t i = 0; i < m; ++i)
+        start[key[in[i]] + 1] += 1;
+    for (uint32_t v = 0; v < n; ++v)
+        start[v + 1] += start[v];
+    for (uint64_t i = 0; i < m; ++i)
+        out[start[key[in[i]]]++] = in[i];
+    free(start);
+    return OR_OK;
 }
 
 void or_graph_free(or_graph* g)
@@ -179,24 +180,27 @@ or_graph* or_graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint
             return NULL;
         }
     }
-    edge_rec* recs = (edge_rec*)malloc((m ? m : 1) * sizeof(edge_rec));
+    /* canonical order: by dst, ties by src (sort by src, then stably by dst) */
+    uint64_t* order = (uint64_t*)malloc((m ? m : 1) * sizeof(uint64_t));
+    uint64_t* by_src = (uint64_t*)malloc((m ? m : 1) * sizeof(uint64_t));
     or_graph* g = (or_graph*)calloc(1, sizeof(or_graph));
-    if (!recs || !g) {
-        free(recs);
-        free(g);
+    if (!order || !by_src || !g) {
+        free(order); free(by_src); free(g);
         *status = OR_ENOMEM;
         return NULL;
     }
-    for (uint64_t i = 0; i < m; ++i) {
-        recs[i].src = src[i];
-        recs[i].dst = dst[i];
-        recs[i].prob = prob[i];
+    for (uint64_t i = 0; i < m; ++i)
+        order[i] = i;
+    if (counting_sort(src, n, m, order, by_src) != OR_OK ||
+        counting_sort(dst, n, m, by_src, order) != OR_OK) {
+        free(order); free(by_src); free(g);
+        *status = OR_ENOMEM;
+        return NULL;
     }
-    qsort(recs, m, sizeof(edge_rec), cmp_dst_src);
-    for (uint64_t i = 1; i < m; ++i) {
-        if (recs[i].src == recs[i - 1].src && recs[i].dst == recs[i - 1].dst) {
-            free(recs);
-            free(g);
+    free(by_src);
+    for (uint64_t e = 1; e < m; ++e) {
+        if (src[order[e]] == src[order[e - 1]] && dst[order[e]] == dst[order[e - 1]]) {
+            free(order); free(g);
             *status = OR_EINVAL;
             return NULL;
         }
@@ -207,19 +211,20 @@ or_graph* or_graph_build(uint32_t n, uint64_t m, const uint32_t* src, const uint
     g->in_src = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
     g->in_thr = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
     if (!g->in_begin || !g->in_src || !g->in_thr) {
-        free(recs);
+        free(order);
         or_graph_free(g);
         *status = OR_ENOMEM;
         return NULL;
     }
     for (uint64_t e = 0; e < m; ++e) {
-        g->in_begin[recs[e].dst + 1] += 1;
-        g->in_src[e] = recs[e].src;
-        g->in_thr[e] = or_thr32(recs[e].prob);
+        uint64_t i = order[e];
+        g->in_begin[dst[i] + 1] += 1;
+        g->in_src[e] = src[i];
+        g->in_thr[e] = or_thr32(prob[i]);
     }
     for (uint32_t v = 0; v < n; ++v)
         g->in_begin[v + 1] += g->in_begin[v];
-    free(recs);
+    free(order);
     return g;
 }
 

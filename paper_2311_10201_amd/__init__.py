@@ -51,7 +51,7 @@ EXPORTED_SYMBOLS = (
 class _Counters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "samples", "members", "sample_edges", "edge_accesses", "frontier_entries", "philox_blocks",
-        "live_coins", "levels", "max_levels", "batches")]
+        "live_coins", "levels", "max_levels", "batches", "traversal_ns", "finalize_ns")]
 
 
 @dataclass
@@ -66,6 +66,8 @@ class Counters:
     levels: int = 0
     max_levels: int = 0
     batches: int = 0
+    traversal_ns: int = 0
+    finalize_ns: int = 0
 
 
 class BptError(RuntimeError):

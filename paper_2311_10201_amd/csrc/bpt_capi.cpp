@@ -80,8 +80,11 @@ struct Workspace {
     uint64_t out_offsets_cap = 0;
     uint32_t* out_vertices = nullptr;
     uint64_t out_vertices_cap = 0;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // traversal start, traversal end, finalize end
 
     ~Workspace() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         dev_free(slot_mem);
         dev_free(ctl);
         if (ctl_host) (void)hipHostFree(ctl_host);
@@ -208,6 +211,7 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
             ws->us.log = reinterpret_cast<uint32_t*>(p);
             ws->us.slots = ws->slots;
         }
+        for (hipEvent_t& e : ws->ev) HIP_TRY(hipEventCreate(&e));
         ws->ctl = dev_alloc<Control>(1);
         HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ws->ctl_host), sizeof(Control), hipHostMallocDefault));
         HIP_TRY(hipDeviceSynchronize());
@@ -308,6 +312,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             capacity = ws->out_vertices_cap;
         }
         HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), stream));
+        HIP_TRY(hipEventRecord(ws->ev[0], stream));
         Output out;
         out.counts = ws->counts;
         out.where = ws->where;
@@ -339,8 +344,10 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             const int grid = (int)std::min<uint64_t>(ws->slots / 4, blocks_needed);
             HIP_TRY(launch_unfused(a, grid, stream));
         }
+        HIP_TRY(hipEventRecord(ws->ev[1], stream));
         HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, ws->ctl,
                                 ws->scratch, ws->scratch_bytes, stream));
+        HIP_TRY(hipEventRecord(ws->ev[2], stream));
         HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const Control& c = *ws->ctl_host;
@@ -365,6 +372,11 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         k.levels = c.stats[kStatLevels];
         k.max_levels = c.stats[kStatMaxLevels];
         k.batches = c.stats[kStatBatches];
+        float ms_trav = 0.f, ms_fin = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms_trav, ws->ev[0], ws->ev[1]));
+        HIP_TRY(hipEventElapsedTime(&ms_fin, ws->ev[1], ws->ev[2]));
+        k.traversal_ns = (uint64_t)((double)ms_trav * 1e6);
+        k.finalize_ns = (uint64_t)((double)ms_fin * 1e6);
         if (c.total > capacity) {
             set_status(BPT_ERANGE, "output capacity " + std::to_string(capacity) + " < " + std::to_string(c.total) +
                                        " members");
