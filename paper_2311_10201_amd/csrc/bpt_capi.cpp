@@ -172,7 +172,7 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
         char* p;
         if (nw > 0) {
             const size_t per = fused_slot_bytes(n, nw) + 256;
-            size_t want = (size_t)g->cus * 2;
+            size_t want = (size_t)g->cus * 4;  // 4 workgroups (16 waves) per CU
             want = std::min(want, std::max<size_t>(1, budget / per));
             ws->slots = (uint32_t)std::max<size_t>(1, want);
             const size_t S = ws->slots, N = n;

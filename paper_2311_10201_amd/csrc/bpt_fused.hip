@@ -40,6 +40,7 @@ constexpr int kWave = 64;
 constexpr int kWaves = kFusedBlock / kWave;
 constexpr int kChunk = kFusedBlock;  // frontier entries staged per pass
 constexpr int kSortCap = 4096;       // touched lists up to this size are sorted in LDS
+constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 template <int NW>
@@ -66,10 +67,10 @@ struct FusedShared {
     } u;
     unsigned long long coff[64 * NW];  // first pool position of each colour's set
     uint32_t cnt[64 * NW];             // members per colour
-    uint32_t qlen[2];
+    uint32_t qlen[3];  // frontier sizes of levels L, L+1 (and L+2, reset), indexed by level % 3
     uint32_t tlen;
     unsigned long long batch;
-    uint32_t scan_tmp[kWaves];
+    uint32_t scan_tmp[2][kWaves];
     unsigned long long base;
     unsigned long long stats[kNumStats];
 };
@@ -87,6 +88,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 }
 
 // Exclusive scan over the workgroup; *total receives the sum (all threads).
+// One barrier: callers alternate between two `tmp` buffers, and at least one
+// other barrier separates two uses of the same buffer.
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp, uint32_t* total) {
     const uint32_t wid = threadIdx.x / kWave;
     const uint32_t incl = wave_incl_scan(x);
@@ -99,7 +102,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp, u
         before += (w < (int)wid) ? t : 0u;
         all += t;
     }
-    __syncthreads();
     *total = all;
     return before + incl - x;
 }
@@ -141,10 +143,11 @@ struct BatchCtx {
 };
 
 // (u, c) became reachable: record it once (Listing 1's visited / frontier
-// update, with the visited mark taken at discovery time).
+// update, with the visited mark taken at discovery time).  `next` is the
+// parity of the level the new frontier entry belongs to, `qslot` its counter.
 template <int NW>
 __device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW>& s, uint32_t u, uint32_t c,
-                                         int next, uint32_t tag) {
+                                         int next, uint32_t qslot, uint32_t tag, uint32_t base_tag) {
     const uint32_t w = c >> 6;
     const unsigned long long bit = 1ull << (c & 63);
     const size_t idx = (size_t)u * NW + w;
@@ -153,21 +156,25 @@ __device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW>&
     atomicAdd(&s.cnt[c], 1u);
     unsigned long long* fr = next ? b.frontier1 : b.frontier0;
     const unsigned long long old_next = atomicOr(&fr[idx], bit);
-    bool push;
+    bool push, first;
     if constexpr (NW == 1) {
+        (void)tag;
+        (void)base_tag;
         push = (old_next == 0);
+        first = (old == 0);
     } else {
         (void)old_next;
-        push = atomicMax(&b.stamp[u], tag) < tag;
+        const uint32_t st = atomicMax(&b.stamp[u], tag);
+        push = st < tag;
+        first = st < base_tag;
     }
     if (push) {
-        const uint32_t pos = atomicAdd(&s.qlen[next], 1u);
+        const uint32_t pos = atomicAdd(&s.qlen[qslot], 1u);
         if (pos < b.n) (next ? b.queue1 : b.queue0)[pos] = u;
         else atomicOr(b.err, (unsigned)kErrQueueOverflow);
     }
-    const unsigned long long tb = 1ull << (u & 63);
-    const unsigned long long old_t = atomicOr(&b.tbits[u >> 6], tb);
-    if (!(old_t & tb)) {
+    if (first) {
+        atomicOr(&b.tbits[u >> 6], 1ull << (u & 63));  // result unused: no wait
         const uint32_t pos = atomicAdd(&s.tlen, 1u);
         if (pos < b.n) b.touched[pos] = u;
         else atomicOr(b.err, (unsigned)kErrQueueOverflow);
@@ -308,28 +315,29 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
         if (tid == 0) {
             s.qlen[0] = 0;
             s.qlen[1] = 0;
+            s.qlen[2] = 0;
             s.tlen = 0;
         }
         __syncthreads();
 
         // Frontier initialisation: colour c starts at its sample's start vertex.
         for (uint32_t c = tid; c < ncol; c += kFusedBlock)
-            discover<NW>(b, s, start_of(s0 + c, n, k0, k1), c, 0, base_tag);
+            discover<NW>(b, s, start_of(s0 + c, n, k0, k1), c, 0, 0, base_tag, base_tag);
 
         // Level-synchronous fused traversal.
-        uint32_t level = 0;
+        uint32_t level = 0, scan_buf = 0;
         unsigned long long th_entries = 0, th_ea = 0, th_te = 0, th_philox = 0, th_live = 0, th_members = 0;
         for (;;) {
-            __syncthreads();
-            const int cur = level & 1, nxt = cur ^ 1;
-            const uint32_t F = min(s.qlen[cur], n);
+            __syncthreads();  // every discovery of the previous level is done
+            const uint32_t qcur = level % 3, qnext = (level + 1) % 3;
+            const uint32_t F = min(s.qlen[qcur], n);
             if (F == 0) break;
             if (level > n) {
                 if (tid == 0) atomicOr(&a.ctl->err, (unsigned)kErrLevelBound);
                 break;
             }
-            __syncthreads();
-            if (tid == 0) s.qlen[nxt] = 0;
+            if (tid == 0) s.qlen[(level + 2) % 3] = 0;  // next used by level L+1's discoveries
+            const int cur = level & 1, nxt = cur ^ 1;
             const uint32_t tag = base_tag + level + 1;
 
             for (uint32_t c0 = 0; c0 < F; c0 += kChunk) {
@@ -351,7 +359,8 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
                     else if (layout == BPT_PROB_UNIFORM) thr = a.g.thr_uniform;
                     const uint32_t deg = end - beg;
                     const bool never = (layout != BPT_PROB_EDGE) && thr == 0;
-                    items = (deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
+                    const uint32_t quads = (deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
+                    items = (quads + kQuadsPerItem - 1) / kQuadsPerItem;
                     s.u.st.v[tid] = v;
                     s.u.st.beg[tid] = beg;
                     s.u.st.end[tid] = end;
@@ -362,48 +371,56 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
                     th_members += pc;
                 }
                 uint32_t total;
-                const uint32_t excl = block_excl_scan(items, s.scan_tmp, &total);
+                const uint32_t excl = block_excl_scan(items, s.scan_tmp[scan_buf], &total);
+                scan_buf ^= 1u;
                 if (tid < cnt) s.u.st.scan[tid] = excl;
                 __syncthreads();
 
                 for (uint32_t t = tid; t < total; t += kFusedBlock) {
                     const uint32_t i = find_entry(s.u.st.scan, cnt, t);
                     const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
-                    const uint32_t quad = (beg >> 2) + (t - s.u.st.scan[i]);
-                    const uint32_t e0 = quad << 2;
-                    uint32_t t0, t1, t2, t3;
-                    if (layout == BPT_PROB_EDGE) {
-                        const uint4 tt = *reinterpret_cast<const uint4*>(a.g.thr_edge + e0);
-                        t0 = tt.x; t1 = tt.y; t2 = tt.z; t3 = tt.w;
-                    } else {
-                        t0 = t1 = t2 = t3 = s.u.st.thr[i];
-                    }
-                    // words of this quad that belong to the row
-                    uint32_t valid = 0xFu;
-                    if (e0 < beg) valid &= 0xFu << (beg - e0);
-                    if (end - e0 < 4) valid &= (1u << (end - e0)) - 1u;
+                    const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * kQuadsPerItem;
+                    const uint32_t q_end = min(q_first + kQuadsPerItem, ((end - 1) >> 2) + 1);
+                    const uint32_t thr_row = s.u.st.thr[i];
+                    unsigned long long mask[NW];
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) {
-                        unsigned long long mk = s.u.st.mask[i][k];
-                        while (mk) {
-                            const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
-                            mk &= mk - 1;
-                            const uint32_t c = (uint32_t)k * 64u + bpos;
-                            const Block4 r = coin_block(quad, s0 + c, k0, k1);
-                            ++th_philox;
-                            uint32_t live = (coin_live(r.w0, t0) ? 1u : 0u) | (coin_live(r.w1, t1) ? 2u : 0u) |
-                                            (coin_live(r.w2, t2) ? 4u : 0u) | (coin_live(r.w3, t3) ? 8u : 0u);
-                            live &= valid;
-                            while (live) {
-                                const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
-                                live &= live - 1;
-                                ++th_live;
-                                discover<NW>(b, s, a.g.col[e0 + j], c, nxt, tag);
+                    for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
+                    for (uint32_t quad = q_first; quad < q_end; ++quad) {
+                        const uint32_t e0 = quad << 2;
+                        uint32_t t0, t1, t2, t3;
+                        if (layout == BPT_PROB_EDGE) {
+                            const uint4 tt = *reinterpret_cast<const uint4*>(a.g.thr_edge + e0);
+                            t0 = tt.x; t1 = tt.y; t2 = tt.z; t3 = tt.w;
+                        } else {
+                            t0 = t1 = t2 = t3 = thr_row;
+                        }
+                        // words of this quad that belong to the row
+                        uint32_t valid = 0xFu;
+                        if (e0 < beg) valid &= 0xFu << (beg - e0);
+                        if (end - e0 < 4) valid &= (1u << (end - e0)) - 1u;
+#pragma unroll
+                        for (int k = 0; k < NW; ++k) {
+                            unsigned long long mk = mask[k];
+                            while (mk) {
+                                const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
+                                mk &= mk - 1;
+                                const uint32_t c = (uint32_t)k * 64u + bpos;
+                                const Block4 r = coin_block(quad, s0 + c, k0, k1);
+                                ++th_philox;
+                                uint32_t live = (coin_live(r.w0, t0) ? 1u : 0u) | (coin_live(r.w1, t1) ? 2u : 0u) |
+                                                (coin_live(r.w2, t2) ? 4u : 0u) | (coin_live(r.w3, t3) ? 8u : 0u);
+                                live &= valid;
+                                while (live) {
+                                    const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
+                                    live &= live - 1;
+                                    ++th_live;
+                                    discover<NW>(b, s, a.g.col[e0 + j], c, nxt, qnext, tag, base_tag);
+                                }
                             }
                         }
                     }
                 }
-                __syncthreads();
+                if (c0 + kChunk < F) __syncthreads();  // the next chunk reuses the staging area
             }
             ++level;
         }
@@ -464,7 +481,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
             uint32_t ones = 0;
             for (size_t w = w0; w < w1; ++w) ones += (uint32_t)__popcll(b.tbits[w]);
             uint32_t all;
-            uint32_t pos = block_excl_scan(ones, s.scan_tmp, &all);
+            uint32_t pos = block_excl_scan(ones, s.scan_tmp[0], &all);
             for (size_t w = w0; w < w1; ++w) {
                 unsigned long long x = b.tbits[w];
                 if (!x) continue;

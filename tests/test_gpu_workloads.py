@@ -1,0 +1,104 @@
+"""GPU parity at the workloads' full sizes.
+
+* R-MAT scale 20, edge factor 16, weighted cascade, 100,000 samples (the
+  benchmark's workload and launch configuration): every set of fused C=64,
+  fused C=256 and unfused equals the oracle's, and the edge-access counters
+  equal the oracle's level-synchronous accounting.
+* R-MAT scale 22, edge factor 16, uniform p = 0.01, 1,000,000 samples fused
+  at C=64: a deterministic subset of sample ids is compared with the oracle
+  one by one (the oracle cannot afford all 10^12 sample-edges), every output
+  set is checked for shape (ascending, in range, start included) on that
+  subset, and fused C=256 / unfused agree with fused C=64 on a prefix.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_2311_10201_amd as bpt
+from gpu_util import announce, assert_same_sets, sample_device
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, len(os.sched_getaffinity(0)))
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    src, dst = graphgen.rmat_graph(20, 16, 0.57, 0.19, 0.19, seed=20)
+    n = 1 << 20
+    prob = graphgen.wc_prob(n, dst)
+    return n, src, dst, prob
+
+
+@pytest.mark.timeout(300)
+def test_rmat20_wc_full(rmat20):
+    n, src, dst, prob = rmat20
+    S, seed = 100_000, 42
+    announce("R-MAT 20 WC: oracle")
+    og = oracle.Graph(n, src, dst, prob)
+    ref = og.sample(seed, S, nthreads=THREADS)
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    assert bpt.bpt_graph_info(g)[2] == bpt.BPT_PROB_ROW
+    te = int(ref.te.sum())
+    for c in (64, 256):
+        announce(f"R-MAT 20 WC S={S} C={c}")
+        off, ver, cnt = sample_device(g, 0, S, c, seed)
+        assert_same_sets(off, ver, ref, f"C={c}")
+        assert cnt.sample_edges == te
+        assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+    announce(f"R-MAT 20 WC S={S} unfused")
+    off, ver, cnt = sample_device(g, 0, S, 0, seed, flags=bpt.BPT_FLAG_UNFUSED)
+    assert_same_sets(off, ver, ref, "unfused")
+    assert cnt.edge_accesses == te
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_p001_sampled():
+    import torch
+    announce("R-MAT 22 p=0.01: generating")
+    src, dst = graphgen.rmat_graph(22, 16, 0.57, 0.19, 0.19, seed=22)
+    n = 1 << 22
+    prob = graphgen.uniform_prob(len(src), 0.01)
+    S, seed = 1_000_000, 42
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    assert bpt.bpt_graph_info(g)[2] == bpt.BPT_PROB_UNIFORM
+    announce(f"R-MAT 22 S={S} C=64")
+    off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    cap = 12_000 * S
+    vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+    st, total, cnt = bpt.bpt_sample_rrr_device(g, 0, S, 64, seed, 0, None, off, vert, cap)
+    assert st == bpt.BPT_OK, total
+    torch.cuda.synchronize()
+    off_h = off.cpu().numpy().view(np.uint64)
+    assert int(off_h[-1]) == total == cnt.members
+    sizes = np.diff(off_h)
+    assert np.all(sizes >= 1)
+    # deterministic subset: every 9973rd sample, plus the largest and smallest sets
+    ids = np.unique(np.concatenate([np.arange(0, S, 9973), [int(np.argmax(sizes)), int(np.argmin(sizes))],
+                                    np.argsort(sizes)[-3:]])).astype(np.uint64)
+    announce(f"R-MAT 22 oracle on {len(ids)} sampled ids")
+    og = oracle.Graph(n, src, dst, prob)
+    ref = og.sample_ids(seed, ids, nthreads=THREADS)
+    for i, s in enumerate(ids.tolist()):
+        got = vert[int(off_h[s]):int(off_h[s + 1])].cpu().numpy().view(np.uint32)
+        want = ref.set_of(i)
+        assert np.array_equal(got, want), f"sample {s}"
+        assert np.all(np.diff(got.astype(np.int64)) > 0) and int(got[-1]) < n
+        assert oracle.start_vertex(seed, s, n) in set(got.tolist())
+    # cross-implementation agreement on a prefix (fresh handle: the first
+    # one's workspaces and output pool are released)
+    P = 50_000
+    head = vert[:int(off_h[P])].cpu().numpy().view(np.uint32)
+    del vert, off
+    bpt.bpt_free(g)
+    torch.cuda.empty_cache()
+    g2 = bpt.bpt_create_graph(n, src, dst, prob)
+    for c, flags in ((256, 0), (0, bpt.BPT_FLAG_UNFUSED)):
+        announce(f"R-MAT 22 prefix S={P} C={c} flags={flags}")
+        o2, v2, _ = sample_device(g2, 0, P, c, seed, flags=flags, capacity=int(off_h[P]))
+        assert np.array_equal(o2, off_h[:P + 1])
+        assert np.array_equal(v2, head)
