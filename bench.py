@@ -99,6 +99,9 @@ def main() -> int:
     ap.add_argument("--colors", type=int, default=0, help="0: pick the fastest listed colour count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (known bytes, for counter scaling)")
+    ap.add_argument("--only", default="", help="time only this variant (fused64, fused256, unfused, ...)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,6 +117,14 @@ def main() -> int:
 
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        a.copy_(b)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read + 1 GiB written")
     log(f"workload {args.workload}: generating graph")
     n, src, dst, prob = make_graph(w)
     m = len(src)
@@ -144,6 +155,11 @@ def main() -> int:
         return (time.perf_counter() - t) / steps, cnts
 
     variants = [(c, 0) for c in w["colors"]] + [(0, bpt.BPT_FLAG_UNFUSED)]
+    if args.only:
+        variants = [v for v in variants if ("unfused" if v[1] else f"fused{v[0]}") == args.only]
+        if not variants:
+            print(f"unknown variant {args.only}", file=sys.stderr)
+            return 2
     warm = {}
     for c, fl in variants:
         name = "unfused" if fl else f"fused{c}"
@@ -154,7 +170,11 @@ def main() -> int:
             warm[name] = time.perf_counter() - t
         log(f"warmup {name}: {warm[name] * 1e3:.2f} ms, members={total}")
 
-    colors = args.colors or min(w["colors"], key=lambda c: warm[f"fused{c}"])
+    fused_done = [c for c in w["colors"] if f"fused{c}" in warm]
+    if not fused_done:
+        print("--only must name a fused variant (the headline is the fused traversal)", file=sys.stderr)
+        return 2
+    colors = args.colors or min(fused_done, key=lambda c: warm[f"fused{c}"])
     log(f"timing fused C={colors}: {args.steps} steps")
     sec, cnts = timed(colors, 0, args.steps)
     cnt = cnts[-1]
@@ -179,6 +199,13 @@ def main() -> int:
                             traversal_ms=sum(x.traversal_ns for x in c2) / len(c2) / 1e6,
                             edge_accesses=c2[-1].edge_accesses)
         log(f"{name}: {s2 * 1e3:.2f} ms/step")
+
+    # host-resident result (adds the device-to-host copy of the CSR over PCIe)
+    bpt.bpt_sample_rrr(g, S, colors, seed)
+    t = time.perf_counter()
+    host_res = bpt.bpt_sample_rrr(g, S, colors, seed)
+    host_s = time.perf_counter() - t
+    host_same = bool(np.array_equal(host_res.offsets, gpu_off) and np.array_equal(host_res.vertices, gpu_ver))
 
     achieved = blocks / trav_s
     traffic = measured_traffic(args.workload, colors)
@@ -226,7 +253,9 @@ def main() -> int:
         "fusion_ratio_te_over_ea": cnt.sample_edges / max(1, cnt.edge_accesses),
         "members": cnt.members,
         "max_levels": cnt.max_levels,
-        "fused_vs_unfused": value / others["unfused"]["samples_per_s"],
+        "fused_vs_unfused": (value / others["unfused"]["samples_per_s"]) if "unfused" in others else None,
+        "host_api": {"samples_per_s": S / host_s, "ms": host_s * 1e3, "same_as_device": host_same,
+                     "note": "bpt_sample_rrr: device sampling plus the device-to-host copy of the CSR"},
         "variants": others,
         "roofline": roofline,
     }

@@ -1,5 +1,6 @@
 // C ABI of libbpt: handles, error state, workspaces and the sampling driver.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -129,6 +130,28 @@ namespace {
 
 bool valid_colors(uint32_t c) { return c == 64 || c == 128 || c == 256 || c == 512 || c == 1024; }
 
+// Fused workers: 4 workgroups of 256 threads per CU (a 128-thread shape with 8
+// per CU exists for tuning through BPT_FUSED_BLOCK; on the R-MAT workloads it
+// is slower: heavy batches need the lanes).
+constexpr int kMaxFusedPerCu = 8;
+
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+
+void fused_launch_shape(const bpt_graph* g, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
+    int bs = env_int("BPT_FUSED_BLOCK", 0);
+    if (bs != 128 && bs != 256) bs = 256;
+    const uint64_t resident = (uint64_t)g->cus * (bs == 128 ? 8 : 4);
+    uint64_t gsz = std::min<uint64_t>({(uint64_t)slots, resident, n_batches});
+    const int cap = env_int("BPT_FUSED_SLOTS", 0);
+    if (cap > 0) gsz = std::min<uint64_t>(gsz, (uint64_t)cap);
+    *block = bs;
+    *grid = (int)std::max<uint64_t>(1, gsz);
+}
+
 DevGraph dev_graph(const bpt_graph* g) {
     DevGraph d;
     d.rowptr = g->d_rowptr;
@@ -171,13 +194,13 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
         const size_t budget = memory_budget();
         char* p;
         if (nw > 0) {
-            const size_t per = fused_slot_bytes(n, nw) + 256;
-            size_t want = (size_t)g->cus * 4;  // 4 workgroups (16 waves) per CU
+            const size_t per = fused_slot_bytes(n, nw) + 1024;
+            size_t want = (size_t)g->cus * kMaxFusedPerCu;
             want = std::min(want, std::max<size_t>(1, budget / per));
             ws->slots = (uint32_t)std::max<size_t>(1, want);
             const size_t S = ws->slots, N = n;
             const size_t words = bitmap_words(n);
-            size_t bytes = S * per + S * 4 + 1024;
+            size_t bytes = S * per + S * 4 + 4096;
             ws->slot_mem = dev_alloc<char>(bytes);
             HIP_TRY(hipMemset(ws->slot_mem, 0, bytes));
             p = static_cast<char*>(ws->slot_mem);
@@ -241,6 +264,7 @@ void release(bpt_graph* g, Workspace* ws) {
     g->idle.push_back(ws);
 }
 
+
 void ensure_sample_arrays(Workspace* ws, uint64_t n_samples) {
     if (ws->sample_cap < n_samples) {
         dev_free(ws->counts);
@@ -292,7 +316,13 @@ void ensure_out(Workspace* ws, uint64_t n_samples, uint64_t entries) {
 struct CallResult {
     uint64_t total = 0;
     bpt_counters counters{};
+    bool discard_workspace = false;
 };
+
+void release_or_discard(bpt_graph* g, Workspace* ws, const CallResult& r) {
+    if (r.discard_workspace) delete ws;
+    else release(g, ws);
+}
 
 // Runs the traversal and the CSR assembly.  When `own_output` is set the
 // result goes to the workspace's own device buffers (sized to fit).
@@ -329,8 +359,9 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.n_samples = S;
             a.colors = colors;
             a.n_batches = (S + colors - 1) / colors;
-            const int grid = (int)std::min<uint64_t>(ws->slots, a.n_batches);
-            HIP_TRY(launch_fused(a, ws->nw, grid, stream));
+            int block = 256, grid = 1;
+            fused_launch_shape(g, ws->slots, a.n_batches, &block, &grid);
+            HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
         } else {
             UnfusedArgs a;
             a.g = dev_graph(g);
@@ -358,6 +389,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         }
         if (c.err) {
             set_status(BPT_EINTERNAL, "device consistency check failed (error bits " + std::to_string(c.err) + ")");
+            res->discard_workspace = true;  // its traversal state may not be clean
             return BPT_EINTERNAL;
         }
         res->total = c.total;
@@ -507,7 +539,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
         const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, unfused, st,
                                     reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity, false,
                                     &res);
-        release(gg, ws);
+        release_or_discard(gg, ws, res);
         ws = nullptr;
         if (rc == BPT_OK || rc == BPT_ERANGE) {
             *total_out = res.total;
@@ -557,8 +589,11 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
             const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, false, nullptr, nullptr, nullptr, 0,
                                         true, &res);
             if (rc != BPT_OK) {
-                release(gg, ws);
+                release_or_discard(gg, ws, res);
+                const int keep_status = t_status;
+                const std::string keep_msg = t_message;
                 bpt_free(r);
+                set_status(keep_status, keep_msg);
                 return nullptr;
             }
             r->total = res.total;

@@ -9,10 +9,10 @@
 //   frontier entry   a vertex v with the mask of colours that reached it at
 //                    the current depth (Listing 1's frontier[v]).
 //   expansion        every in-edge e = (u -> v) of the entry is tried for
-//                    every colour of the mask.  Work items are (entry,
-//                    4-edge quad) pairs spread evenly over the workgroup's
-//                    lanes; each item evaluates one Philox block per colour,
-//                    which yields the coins of all four edges of the quad.
+//                    every colour of the mask.  Work items are (entry, up to
+//                    four 4-edge quads) spread evenly over the workgroup's
+//                    lanes; each evaluates one Philox block per colour and
+//                    quad, i.e. the coins of four consecutive in-edges.
 //                    Coins are flipped before any neighbour data is read
 //                    ("flip before gather"): `col[e]` and visited[u] are only
 //                    touched for live coins.
@@ -37,40 +37,40 @@ namespace bpt {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kWaves = kFusedBlock / kWave;
-constexpr int kChunk = kFusedBlock;  // frontier entries staged per pass
-constexpr int kSortCap = 4096;       // touched lists up to this size are sorted in LDS
-constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
+// Workgroup size BS is a template parameter (128 or 256 threads); a chunk of
+// BS frontier entries is staged per pass, and touched lists up to
+// sort_cap(BS) vertices are sorted in LDS.
+constexpr int sort_cap(int bs) { return bs >= 256 ? 4096 : 2048; }
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
 
-template <int NW>
+template <int NW, int BS>
 struct Stage {  // traversal staging of one chunk of frontier entries
-    uint32_t v[kChunk];
-    uint32_t beg[kChunk];
-    uint32_t end[kChunk];
-    uint32_t thr[kChunk];
-    uint32_t scan[kChunk];
-    unsigned long long mask[kChunk][NW];
+    uint32_t beg[BS];
+    uint32_t end[BS];
+    uint32_t thr[BS];
+    uint32_t scan[BS];
+    unsigned long long mask[BS][NW];
 };
 
-template <int NW>
+template <int NW, int BS>
 struct Extract {  // extraction buffers
-    uint32_t sorted[kSortCap];
-    uint32_t wprefix[kWaves][64 * NW];
+    uint32_t sorted[sort_cap(BS)];
+    uint32_t wprefix[BS / kWave][64 * NW];
 };
 
-template <int NW>
+template <int NW, int BS>
 struct FusedShared {
     union {
-        Stage<NW> st;
-        Extract<NW> ex;
+        Stage<NW, BS> st;
+        Extract<NW, BS> ex;
     } u;
     unsigned long long coff[64 * NW];  // first pool position of each colour's set
-    uint32_t cnt[64 * NW];             // members per colour
+    uint32_t cnt[64 * NW];             // members per colour (found by this workgroup)
     uint32_t qlen[3];  // frontier sizes of levels L, L+1 (and L+2, reset), indexed by level % 3
     uint32_t tlen;
     unsigned long long batch;
-    uint32_t scan_tmp[2][kWaves];
+    uint32_t scan_tmp[2][BS / kWave];
     unsigned long long base;
     unsigned long long stats[kNumStats];
 };
@@ -90,7 +90,9 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // Exclusive scan over the workgroup; *total receives the sum (all threads).
 // One barrier: callers alternate between two `tmp` buffers, and at least one
 // other barrier separates two uses of the same buffer.
+template <int BS>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* tmp, uint32_t* total) {
+    constexpr int kWaves = BS / kWave;
     const uint32_t wid = threadIdx.x / kWave;
     const uint32_t incl = wave_incl_scan(x);
     if (lane_id() == kWave - 1) tmp[wid] = incl;
@@ -127,26 +129,69 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// State of the batch a workgroup is working on.
+// Wavefront issue priority (s_setprio) among the waves resident on a SIMD.
+__device__ __forceinline__ void set_wave_priority(int p) {
+    switch (p) {
+        case 3: __builtin_amdgcn_s_setprio(3); break;
+        case 2: __builtin_amdgcn_s_setprio(2); break;
+        case 1: __builtin_amdgcn_s_setprio(1); break;
+        default: __builtin_amdgcn_s_setprio(0); break;
+    }
+}
+
+// The slot's traversal state is written with device-scope atomics.  It is
+// read back and cleared with agent-scope (device-coherent) loads and stores
+// after waiting for this workgroup's own atomics (s_waitcnt): an agent-scope
+// acquire/release fence would write back or invalidate a whole L2 on this
+// multi-XCD part.
+__device__ __forceinline__ void store_coherent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_own_memory_ops() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ __forceinline__ unsigned long long load_coherent64(const unsigned long long* p) {
+    return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent64(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Traversal state of one slot.
 template <int NW>
 struct BatchCtx {
-    unsigned long long* visited;  // n * NW
+    unsigned long long* visited;    // n * NW
     unsigned long long* frontier0;  // frontier masks of even levels
     unsigned long long* frontier1;  // frontier masks of odd levels
     uint32_t* stamp;
-    uint32_t* queue0;
-    uint32_t* queue1;
-    uint32_t* touched;
+    uint32_t* queue0;   // frontier queue of even levels
+    uint32_t* queue1;   // frontier queue of odd levels
+    uint32_t* touched;  // vertices touched by the batch, in discovery order
     unsigned long long* tbits;
     uint32_t n;
     unsigned int* err;
 };
 
+template <int NW>
+__device__ __forceinline__ BatchCtx<NW> slot_ctx(const FusedArgs& a, uint32_t slot) {
+    const uint32_t n = a.g.n;
+    BatchCtx<NW> b;
+    b.n = n;
+    b.err = &a.ctl->err;
+    b.visited = a.ws.visited + (size_t)slot * n * NW;
+    b.frontier0 = a.ws.frontier + (size_t)slot * 2 * n * NW;
+    b.frontier1 = b.frontier0 + (size_t)n * NW;
+    b.stamp = (NW > 1) ? a.ws.stamp + (size_t)slot * n : nullptr;
+    b.queue0 = a.ws.queue + (size_t)slot * 2 * n;
+    b.queue1 = b.queue0 + n;
+    b.touched = a.ws.touched + (size_t)slot * n;
+    b.tbits = a.ws.tbits + (size_t)slot * bitmap_words(n);
+    return b;
+}
+
 // (u, c) became reachable: record it once (Listing 1's visited / frontier
 // update, with the visited mark taken at discovery time).  `next` is the
 // parity of the level the new frontier entry belongs to, `qslot` its counter.
-template <int NW>
-__device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW>& s, uint32_t u, uint32_t c,
+template <int NW, int BS>
+__device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW, BS>& s, uint32_t u, uint32_t c,
                                          int next, uint32_t qslot, uint32_t tag, uint32_t base_tag) {
     const uint32_t w = c >> 6;
     const unsigned long long bit = 1ull << (c & 63);
@@ -181,6 +226,53 @@ __device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW>&
     }
 }
 
+// Coins of quads [q_first, q_end) of the row [beg, end) for every colour in
+// `mask`, and discovery of the live ones.
+template <int NW, int BS>
+__device__ __forceinline__ void expand_quads(const FusedArgs& a, const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
+                                             const unsigned long long (&mask)[NW], unsigned long long s0,
+                                             uint32_t beg, uint32_t end, uint32_t thr_row, uint32_t q_first,
+                                             uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
+                                             uint32_t base_tag, unsigned long long& n_philox,
+                                             unsigned long long& n_live) {
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t layout = a.g.prob_layout;
+    for (uint32_t quad = q_first; quad < q_end; ++quad) {
+        const uint32_t e0 = quad << 2;
+        uint32_t t0, t1, t2, t3;
+        if (layout == BPT_PROB_EDGE) {
+            const uint4 tt = *reinterpret_cast<const uint4*>(a.g.thr_edge + e0);
+            t0 = tt.x; t1 = tt.y; t2 = tt.z; t3 = tt.w;
+        } else {
+            t0 = t1 = t2 = t3 = thr_row;
+        }
+        // words of this quad that belong to the row
+        uint32_t valid = 0xFu;
+        if (e0 < beg) valid &= 0xFu << (beg - e0);
+        if (end - e0 < 4) valid &= (1u << (end - e0)) - 1u;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            unsigned long long mk = mask[k];
+            while (mk) {
+                const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
+                mk &= mk - 1;
+                const uint32_t c = (uint32_t)k * 64u + bpos;
+                const Block4 r = coin_block(quad, s0 + c, k0, k1);
+                ++n_philox;
+                uint32_t live = (coin_live(r.w0, t0) ? 1u : 0u) | (coin_live(r.w1, t1) ? 2u : 0u) |
+                                (coin_live(r.w2, t2) ? 4u : 0u) | (coin_live(r.w3, t3) ? 8u : 0u);
+                live &= valid;
+                while (live) {
+                    const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
+                    live &= live - 1;
+                    ++n_live;
+                    discover<NW, BS>(b, s, a.g.col[e0 + j], c, nxt, qslot, tag, base_tag);
+                }
+            }
+        }
+    }
+}
+
 // Largest i in [0, cnt) with scan[i] <= t (scan is an exclusive prefix).
 __device__ __forceinline__ uint32_t find_entry(const uint32_t* scan, uint32_t cnt, uint32_t t) {
     uint32_t lo = 0, hi = cnt;  // answer in [lo, hi)
@@ -194,9 +286,10 @@ __device__ __forceinline__ uint32_t find_entry(const uint32_t* scan, uint32_t cn
 
 // Writes each colour's members (ascending) from the sorted vertex list
 // `list[0..T)` into the pool and clears visited[] for the listed vertices.
-template <int NW>
-__device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW>& s, const uint32_t* list,
+template <int NW, int BS>
+__device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW, BS>& s, const uint32_t* list,
                            uint32_t T, bool write_ok) {
+    constexpr int kWaves = BS / kWave;
     const uint32_t lane = lane_id();
     const uint32_t wid = threadIdx.x / kWave;
     const uint32_t nchunks = (T + kWave - 1) / kWave;
@@ -214,7 +307,7 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
         const uint32_t u = idx < T ? list[idx] : kNone;
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
-            const unsigned long long mk = (u != kNone) ? b.visited[(size_t)u * NW + k] : 0ull;
+            const unsigned long long mk = (u != kNone) ? load_coherent64(&b.visited[(size_t)u * NW + k]) : 0ull;
             unsigned long long present = wave_or64(mk);
             while (present) {
                 const int bpos = __ffsll((long long)present) - 1;
@@ -227,7 +320,7 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
 #pragma unroll
     for (int k = 0; k < NW; ++k) s.u.ex.wprefix[wid][k * 64 + lane] = mycnt[k];
     __syncthreads();
-    for (uint32_t c = threadIdx.x; c < 64u * NW; c += kFusedBlock) {
+    for (uint32_t c = threadIdx.x; c < 64u * NW; c += BS) {
         uint32_t run = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -248,7 +341,7 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
         const uint32_t u = idx < T ? list[idx] : kNone;
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
-            const unsigned long long mk = (u != kNone) ? b.visited[(size_t)u * NW + k] : 0ull;
+            const unsigned long long mk = (u != kNone) ? load_coherent64(&b.visited[(size_t)u * NW + k]) : 0ull;
             unsigned long long present = wave_or64(mk);
             while (present) {
                 const int bpos = __ffsll((long long)present) - 1;
@@ -262,39 +355,31 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
         }
         if (u != kNone) {
 #pragma unroll
-            for (int k = 0; k < NW; ++k) b.visited[(size_t)u * NW + k] = 0ull;
+            for (int k = 0; k < NW; ++k) store_coherent64(&b.visited[(size_t)u * NW + k], 0ull);
         }
     }
 }
 
-template <int NW>
-__global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
-    __shared__ FusedShared<NW> s;
+template <int NW, int BS>
+__global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
+    __shared__ FusedShared<NW, BS> s;
+    constexpr uint32_t kSortCap = sort_cap(BS);
     const uint32_t tid = threadIdx.x;
     const uint32_t n = a.g.n;
     const uint32_t slot = blockIdx.x;
     constexpr uint32_t C = 64u * NW;
-
-    BatchCtx<NW> b;
-    b.n = n;
-    b.err = &a.ctl->err;
-    b.visited = a.ws.visited + (size_t)slot * n * NW;
-    b.frontier0 = a.ws.frontier + (size_t)slot * 2 * n * NW;
-    b.frontier1 = b.frontier0 + (size_t)n * NW;
-    b.stamp = (NW > 1) ? a.ws.stamp + (size_t)slot * n : nullptr;
-    b.queue0 = a.ws.queue + (size_t)slot * 2 * n;
-    b.queue1 = b.queue0 + n;
-    b.touched = a.ws.touched + (size_t)slot * n;
-    b.tbits = a.ws.tbits + (size_t)slot * bitmap_words(n);
-
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const BatchCtx<NW> b = slot_ctx<NW>(a, slot);
     const uint32_t layout = a.g.prob_layout;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
 
     if (tid < kNumStats) s.stats[tid] = 0;
+    unsigned long long th_entries = 0, th_ea = 0, th_te = 0, th_philox = 0, th_live = 0, th_members = 0;
 
     for (;;) {
         __syncthreads();
-        if (tid == 0) s.batch = atomicAdd(&a.ctl->work_counter, 1ull);
+        if (tid == 0) {
+            s.batch = atomicAdd(&a.ctl->work_counter, 1ull);
+        }
         __syncthreads();
         const uint64_t batch = s.batch;
         if (batch >= a.n_batches) break;
@@ -305,13 +390,13 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
         if constexpr (NW > 1) {
             base_tag = a.ws.slot_tag[slot] + 1;
             if (base_tag > 0xFFFFFFFFu - n - 8u) {  // tags would wrap: restart them
-                for (uint32_t v = tid; v < n; v += kFusedBlock) b.stamp[v] = 0;
-                __threadfence();
+                for (uint32_t v = tid; v < n; v += BS) store_coherent(&b.stamp[v], 0u);
+                wait_own_memory_ops();
                 __syncthreads();
                 base_tag = 1;
             }
         }
-        for (uint32_t c = tid; c < C; c += kFusedBlock) s.cnt[c] = 0;
+        for (uint32_t c = tid; c < C; c += BS) s.cnt[c] = 0;
         if (tid == 0) {
             s.qlen[0] = 0;
             s.qlen[1] = 0;
@@ -321,12 +406,11 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
         __syncthreads();
 
         // Frontier initialisation: colour c starts at its sample's start vertex.
-        for (uint32_t c = tid; c < ncol; c += kFusedBlock)
-            discover<NW>(b, s, start_of(s0 + c, n, k0, k1), c, 0, 0, base_tag, base_tag);
+        for (uint32_t c = tid; c < ncol; c += BS)
+            discover<NW, BS>(b, s, start_of(s0 + c, n, k0, k1), c, 0, 0, base_tag, base_tag);
 
         // Level-synchronous fused traversal.
         uint32_t level = 0, scan_buf = 0;
-        unsigned long long th_entries = 0, th_ea = 0, th_te = 0, th_philox = 0, th_live = 0, th_members = 0;
         for (;;) {
             __syncthreads();  // every discovery of the previous level is done
             const uint32_t qcur = level % 3, qnext = (level + 1) % 3;
@@ -336,15 +420,18 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
                 if (tid == 0) atomicOr(&a.ctl->err, (unsigned)kErrLevelBound);
                 break;
             }
-            if (tid == 0) s.qlen[(level + 2) % 3] = 0;  // next used by level L+1's discoveries
+            if (tid == 0) {
+                s.qlen[(level + 2) % 3] = 0;  // used next by level L+1's discoveries
+            }
             const int cur = level & 1, nxt = cur ^ 1;
             const uint32_t tag = base_tag + level + 1;
+            const uint32_t* qcur_arr = cur ? b.queue1 : b.queue0;
 
-            for (uint32_t c0 = 0; c0 < F; c0 += kChunk) {
-                const uint32_t cnt = min((uint32_t)kChunk, F - c0);
+            for (uint32_t c0 = 0; c0 < F; c0 += BS) {
+                const uint32_t cnt = min((uint32_t)BS, F - c0);
                 uint32_t items = 0;
                 if (tid < cnt) {
-                    const uint32_t v = (cur ? b.queue1 : b.queue0)[c0 + tid];
+                    const uint32_t v = qcur_arr[c0 + tid];
                     const uint32_t beg = a.g.rowptr[v], end = a.g.rowptr[v + 1];
                     uint32_t pc = 0;
 #pragma unroll
@@ -361,7 +448,6 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
                     const bool never = (layout != BPT_PROB_EDGE) && thr == 0;
                     const uint32_t quads = (deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
                     items = (quads + kQuadsPerItem - 1) / kQuadsPerItem;
-                    s.u.st.v[tid] = v;
                     s.u.st.beg[tid] = beg;
                     s.u.st.end[tid] = end;
                     s.u.st.thr[tid] = thr;
@@ -371,62 +457,34 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
                     th_members += pc;
                 }
                 uint32_t total;
-                const uint32_t excl = block_excl_scan(items, s.scan_tmp[scan_buf], &total);
+                const uint32_t excl = block_excl_scan<BS>(items, s.scan_tmp[scan_buf], &total);
                 scan_buf ^= 1u;
                 if (tid < cnt) s.u.st.scan[tid] = excl;
                 __syncthreads();
 
-                for (uint32_t t = tid; t < total; t += kFusedBlock) {
+                // Heavy expansion levels are compute-bound while light ones wait on
+                // memory: give the heavy ones issue priority on their SIMDs.
+                set_wave_priority(total >= 8u * BS ? 3 : (total >= 2u * BS ? 2 : (total >= BS / 2 ? 1 : 0)));
+                for (uint32_t t = tid; t < total; t += BS) {
                     const uint32_t i = find_entry(s.u.st.scan, cnt, t);
                     const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
                     const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * kQuadsPerItem;
                     const uint32_t q_end = min(q_first + kQuadsPerItem, ((end - 1) >> 2) + 1);
-                    const uint32_t thr_row = s.u.st.thr[i];
                     unsigned long long mask[NW];
 #pragma unroll
                     for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
-                    for (uint32_t quad = q_first; quad < q_end; ++quad) {
-                        const uint32_t e0 = quad << 2;
-                        uint32_t t0, t1, t2, t3;
-                        if (layout == BPT_PROB_EDGE) {
-                            const uint4 tt = *reinterpret_cast<const uint4*>(a.g.thr_edge + e0);
-                            t0 = tt.x; t1 = tt.y; t2 = tt.z; t3 = tt.w;
-                        } else {
-                            t0 = t1 = t2 = t3 = thr_row;
-                        }
-                        // words of this quad that belong to the row
-                        uint32_t valid = 0xFu;
-                        if (e0 < beg) valid &= 0xFu << (beg - e0);
-                        if (end - e0 < 4) valid &= (1u << (end - e0)) - 1u;
-#pragma unroll
-                        for (int k = 0; k < NW; ++k) {
-                            unsigned long long mk = mask[k];
-                            while (mk) {
-                                const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
-                                mk &= mk - 1;
-                                const uint32_t c = (uint32_t)k * 64u + bpos;
-                                const Block4 r = coin_block(quad, s0 + c, k0, k1);
-                                ++th_philox;
-                                uint32_t live = (coin_live(r.w0, t0) ? 1u : 0u) | (coin_live(r.w1, t1) ? 2u : 0u) |
-                                                (coin_live(r.w2, t2) ? 4u : 0u) | (coin_live(r.w3, t3) ? 8u : 0u);
-                                live &= valid;
-                                while (live) {
-                                    const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
-                                    live &= live - 1;
-                                    ++th_live;
-                                    discover<NW>(b, s, a.g.col[e0 + j], c, nxt, qnext, tag, base_tag);
-                                }
-                            }
-                        }
-                    }
+                    expand_quads<NW, BS>(a, b, s, mask, s0, beg, end, s.u.st.thr[i], q_first, q_end, nxt,
+                                                qnext, tag, base_tag, th_philox, th_live);
                 }
-                if (c0 + kChunk < F) __syncthreads();  // the next chunk reuses the staging area
+                set_wave_priority(0);
+                if (c0 + BS < F) __syncthreads();  // the next chunk reuses the staging area
             }
+
             ++level;
         }
 
         // ---- RRR set extraction (Listing 1's final loop) ----
-        __threadfence();  // atomics above completed in L2; drop stale L1 lines
+        wait_own_memory_ops();  // this workgroup's last atomics have been performed
         __syncthreads();
         const uint32_t T = min(s.tlen, n);
         if (tid == 0) {
@@ -444,20 +502,21 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
         }
         __syncthreads();
         const bool write_ok = s.base + s.coff[C - 1] + s.cnt[C - 1] <= a.out.pool_cap;
-        for (uint32_t c = tid; c < ncol; c += kFusedBlock) {
+        for (uint32_t c = tid; c < ncol; c += BS) {
             a.out.counts[s0 - a.first_sample + c] = s.cnt[c];
             a.out.where[s0 - a.first_sample + c] = s.base + s.coff[c];
         }
 
         const uint32_t* list;
-        if (T <= (uint32_t)kSortCap) {
+        if (T <= kSortCap) {
             uint32_t P = 64;
             while (P < T) P <<= 1;
-            for (uint32_t i = tid; i < P; i += kFusedBlock) s.u.ex.sorted[i] = i < T ? b.touched[i] : kNone;
+            for (uint32_t i = tid; i < P; i += BS)
+                s.u.ex.sorted[i] = i < T ? b.touched[i] : kNone;
             __syncthreads();
             for (uint32_t k = 2; k <= P; k <<= 1) {
                 for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t i = tid; i < P; i += kFusedBlock) {
+                    for (uint32_t i = tid; i < P; i += BS) {
                         const uint32_t ixj = i ^ j;
                         if (ixj > i) {
                             const uint32_t x = s.u.ex.sorted[i], y = s.u.ex.sorted[ixj];
@@ -471,21 +530,21 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
                     __syncthreads();
                 }
             }
-            for (uint32_t i = tid; i < T; i += kFusedBlock) b.tbits[s.u.ex.sorted[i] >> 6] = 0ull;
+            for (uint32_t i = tid; i < T; i += BS) store_coherent64(&b.tbits[s.u.ex.sorted[i] >> 6], 0ull);
             list = s.u.ex.sorted;
         } else {
             // touched-vertex bitmap, scanned in vertex order, gives the sorted list
             const size_t words = bitmap_words(n);
-            const size_t per_t = (words + kFusedBlock - 1) / kFusedBlock;
+            const size_t per_t = (words + BS - 1) / BS;
             const size_t w0 = min(words, (size_t)tid * per_t), w1 = min(words, w0 + per_t);
             uint32_t ones = 0;
-            for (size_t w = w0; w < w1; ++w) ones += (uint32_t)__popcll(b.tbits[w]);
+            for (size_t w = w0; w < w1; ++w) ones += (uint32_t)__popcll(load_coherent64(&b.tbits[w]));
             uint32_t all;
-            uint32_t pos = block_excl_scan(ones, s.scan_tmp[0], &all);
+            uint32_t pos = block_excl_scan<BS>(ones, s.scan_tmp[scan_buf], &all);
             for (size_t w = w0; w < w1; ++w) {
-                unsigned long long x = b.tbits[w];
+                unsigned long long x = load_coherent64(&b.tbits[w]);
                 if (!x) continue;
-                b.tbits[w] = 0ull;
+                store_coherent64(&b.tbits[w], 0ull);
                 while (x) {
                     const uint32_t bpos = (uint32_t)(__ffsll((long long)x) - 1);
                     x &= x - 1;
@@ -497,16 +556,17 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
             list = b.touched;
         }
         __syncthreads();
-        write_sets<NW>(a.out.pool, b, s, list, T, write_ok);
-        // thread-local counters into the workgroup's totals
-        atomicAdd(&s.stats[kStatEntries], th_entries);
-        atomicAdd(&s.stats[kStatEdgeAccesses], th_ea);
-        atomicAdd(&s.stats[kStatSampleEdges], th_te);
-        atomicAdd(&s.stats[kStatPhilox], th_philox);
-        atomicAdd(&s.stats[kStatLive], th_live);
-        atomicAdd(&s.stats[kStatMembers], th_members);
-        __threadfence();  // resets reach L2 before the next batch's atomics
+        write_sets<NW, BS>(a.out.pool, b, s, list, T, write_ok);
+        wait_own_memory_ops();  // the slot's resets have been performed before it is reused
     }
+
+    // thread-local counters into the workgroup's totals, then the call's
+    atomicAdd(&s.stats[kStatEntries], th_entries);
+    atomicAdd(&s.stats[kStatEdgeAccesses], th_ea);
+    atomicAdd(&s.stats[kStatSampleEdges], th_te);
+    atomicAdd(&s.stats[kStatPhilox], th_philox);
+    atomicAdd(&s.stats[kStatLive], th_live);
+    atomicAdd(&s.stats[kStatMembers], th_members);
     __syncthreads();
     if (tid < kNumStats) {
         if (tid == kStatMaxLevels) atomicMax(&a.ctl->stats[tid], s.stats[tid]);
@@ -516,15 +576,31 @@ __global__ __launch_bounds__(kFusedBlock) void fused_bpt_kernel(FusedArgs a) {
 
 }  // namespace
 
-hipError_t launch_fused(const FusedArgs& a, int nw, int grid, hipStream_t stream) {
-    switch (nw) {
-        case 1: hipLaunchKernelGGL(fused_bpt_kernel<1>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL(fused_bpt_kernel<2>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
-        case 4: hipLaunchKernelGGL(fused_bpt_kernel<4>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
-        case 8: hipLaunchKernelGGL(fused_bpt_kernel<8>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
-        case 16: hipLaunchKernelGGL(fused_bpt_kernel<16>, dim3(grid), dim3(kFusedBlock), 0, stream, a); break;
-        default: return hipErrorInvalidValue;
+hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStream_t stream) {
+#define BPT_LAUNCH(NW_, BS_) \
+    hipLaunchKernelGGL((fused_bpt_kernel<NW_, BS_>), dim3(grid), dim3(BS_), 0, stream, a)
+    if (block == 128) {
+        switch (nw) {
+            case 1: BPT_LAUNCH(1, 128); break;
+            case 2: BPT_LAUNCH(2, 128); break;
+            case 4: BPT_LAUNCH(4, 128); break;
+            case 8: BPT_LAUNCH(8, 128); break;
+            case 16: BPT_LAUNCH(16, 128); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (block == 256) {
+        switch (nw) {
+            case 1: BPT_LAUNCH(1, 256); break;
+            case 2: BPT_LAUNCH(2, 256); break;
+            case 4: BPT_LAUNCH(4, 256); break;
+            case 8: BPT_LAUNCH(8, 256); break;
+            case 16: BPT_LAUNCH(16, 256); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
     }
+#undef BPT_LAUNCH
     return hipGetLastError();
 }
 

@@ -105,7 +105,7 @@ struct UnfusedArgs {
 __host__ __device__ inline size_t bitmap_words(uint32_t n) { return ((size_t)n + 63) / 64; }
 
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_fused(const FusedArgs& a, int nw, int grid, hipStream_t stream);
+hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStream_t stream);
 hipError_t launch_unfused(const UnfusedArgs& a, int grid, hipStream_t stream);
 hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
                            uint64_t n_samples, unsigned long long* offsets, uint32_t* vertices,
@@ -113,7 +113,6 @@ hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* whe
                            hipStream_t stream);
 size_t finalize_scratch_bytes(uint64_t n_samples);
 
-constexpr int kFusedBlock = 256;    // threads per fused workgroup
 constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
 
 }  // namespace bpt

@@ -33,6 +33,15 @@ struct WaveShared {
     uint32_t tail;
 };
 
+// The visited bitmap is written by atomics; it is read and cleared with
+// agent-scope (device-coherent) loads and stores, so no L2-wide fence is needed.
+__device__ __forceinline__ unsigned long long load_coherent64(const unsigned long long* p) {
+    return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent64(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(kUnfusedBlock) void unfused_bpt_kernel(UnfusedArgs 
         base = ((unsigned long long)__shfl((uint32_t)(base >> 32), 0, kWave) << 32) |
                __shfl((uint32_t)base, 0, kWave);
         const bool write_ok = base + T <= a.out.pool_cap;
-        __threadfence();  // bitmap atomics completed in L2; drop stale L1 lines
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's bitmap atomics have been performed
         if (T <= kWaveSortCap) {
             uint32_t P = kWave;
             while (P < T) P <<= 1;
@@ -206,18 +215,18 @@ __global__ __launch_bounds__(kUnfusedBlock) void unfused_bpt_kernel(UnfusedArgs 
             for (uint32_t i = lane; i < T; i += kWave) {
                 const uint32_t u = w.sorted[i];
                 if (write_ok) a.out.pool[base + i] = u;
-                vbits[u >> 6] = 0ull;
+                store_coherent64(&vbits[u >> 6], 0ull);
             }
         } else {
             unsigned long long run = 0;
             for (size_t w0 = 0; w0 < words; w0 += kWave) {
                 const size_t wi = w0 + lane;
-                unsigned long long x = wi < words ? vbits[wi] : 0ull;
+                unsigned long long x = wi < words ? load_coherent64(&vbits[wi]) : 0ull;
                 const uint32_t pc = (uint32_t)__popcll(x);
                 const uint32_t incl = wave_incl_scan(pc, lane);
                 const uint32_t tot = __shfl(incl, kWave - 1, kWave);
                 unsigned long long pos = base + run + (incl - pc);
-                if (x) vbits[wi] = 0ull;
+                if (x) store_coherent64(&vbits[wi], 0ull);
                 while (x) {
                     const uint32_t bpos = (uint32_t)(__ffsll((long long)x) - 1);
                     x &= x - 1;
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(kUnfusedBlock) void unfused_bpt_kernel(UnfusedArgs 
                 run += tot;
             }
         }
-        __threadfence();  // cleared bitmap reaches L2 before the next sample's atomics
+        __builtin_amdgcn_s_waitcnt(0);  // the cleared bitmap is performed before the next sample
         wave_sync();
         st_members += T;
         st_levels += level;

@@ -176,3 +176,49 @@ def test_invalid_sampling_arguments(er_case):
         assert ei.value.status == bpt.BPT_EINVAL
     with pytest.raises(bpt.BptError):
         bpt.bpt_sample_rrr(g, 1 << 34, 64, 1)
+
+
+def hub_graph(n=20_000, hubs=12, hub_in=9_000, hub_out=1_500, m_rand=60_000, seed=17):
+    """Random graph plus hub vertices with thousands of in-edges (rows that the
+    fused kernel splits into device-wide tasks) and many out-edges (so samples
+    reach them often)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = [rng.integers(0, n, m_rand)]
+    dst = [rng.integers(0, n, m_rand)]
+    for h in range(hubs):
+        src.append(rng.integers(0, n, hub_in))
+        dst.append(np.full(hub_in, h))
+        src.append(np.full(hub_out, h))
+        dst.append(rng.integers(0, n, hub_out))
+    key = np.unique((np.concatenate(src).astype(np.uint64) << np.uint64(32)) | np.concatenate(dst).astype(np.uint64))
+    s = (key >> np.uint64(32)).astype(np.uint32)
+    d = (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    keep = s != d
+    return n, s[keep], d[keep]
+
+
+@pytest.mark.parametrize("layout", ["uniform", "row", "edge"])
+def test_hub_rows_split_across_workgroups(layout):
+    n, src, dst = hub_graph()
+    if layout == "uniform":
+        prob = graphgen.uniform_prob(len(src), 0.02)
+    elif layout == "row":
+        prob = graphgen.wc_prob(n, dst)
+    else:
+        prob = (np.random.Generator(np.random.PCG64(8)).random(len(src), dtype=np.float32)
+                * np.float32(0.05)).astype(np.float32)
+    announce(f"hub graph layout={layout} n={n} m={len(src)}")
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    og = oracle.Graph(n, src, dst, prob)
+    S = 3000
+    ref = og.sample(23, S, nthreads=8)
+    indeg = og.indegree()
+    hub_expansions = int(np.sum(indeg[ref.members.astype(np.int64)] >= 4096))
+    assert hub_expansions > 100  # the split path is exercised
+    for c in COLORS:
+        off, ver, cnt = sample_device(g, 0, S, c, 23)
+        assert_same_sets(off, ver, ref, f"hub {layout} C={c}")
+        assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+        assert cnt.sample_edges == int(ref.te.sum())
+    off, ver, _ = sample_device(g, 0, S, 0, 23, flags=bpt.BPT_FLAG_UNFUSED)
+    assert_same_sets(off, ver, ref, f"hub {layout} unfused")
