@@ -187,6 +187,12 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
  * pointer may be NULL.  Returns BPT_OK or BPT_EINVAL. */
 int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_layout);
 
+/* Frees the device memory the graph keeps cached between calls: traversal
+ * workspaces and output pools (tens of GB for graphs with millions of
+ * vertices).  Calls in flight on other threads keep theirs.  The next sampling
+ * call allocates again.  Returns BPT_OK or BPT_EINVAL. */
+int bpt_graph_release_cache(bpt_graph* g);
+
 /* Colour count the library uses for colors_per_batch = 0 on this graph for a
  * job of n_samples samples (64 .. 1024). */
 uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples);

@@ -21,6 +21,7 @@ __all__ = [
     "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED",
     "BptError", "Counters", "Graph", "RRRResult",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_graph_info",
+    "bpt_graph_release_cache",
     "bpt_default_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
     "bpt_last_status", "bpt_last_error", "library_path", "load_library",
 ]
@@ -44,7 +45,8 @@ _lib = None
 EXPORTED_SYMBOLS = (
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_rrr_num_samples", "bpt_rrr_num_members",
     "bpt_rrr_offsets", "bpt_rrr_vertices", "bpt_last_status", "bpt_last_error", "bpt_sample_rrr_device",
-    "bpt_graph_info", "bpt_default_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
+    "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_thr32", "bpt_coin_word",
+    "bpt_start_vertex", "bpt_version",
 )
 
 
@@ -109,6 +111,7 @@ def load_library():
         "bpt_sample_rrr_device": (i32, [vp, u64, u64, u32, u64, u32, vp, vp, vp, u64,
                                         ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
+        "bpt_graph_release_cache": (i32, [vp]),
         "bpt_default_colors": (u32, [vp, u64]),
         "bpt_thr32": (u32, [ctypes.c_float]),
         "bpt_coin_word": (u32, [u64, u64, u64]),
@@ -257,6 +260,11 @@ def bpt_graph_info(graph: Graph):
     if lib.bpt_graph_info(graph.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(lay)) != BPT_OK:
         _raise_last()
     return int(n.value), int(m.value), int(lay.value)
+
+
+def bpt_graph_release_cache(graph: Graph) -> None:
+    if load_library().bpt_graph_release_cache(graph.handle) != BPT_OK:
+        _raise_last()
 
 
 def bpt_default_colors(graph: Graph, n_samples: int) -> int:

@@ -82,6 +82,14 @@ struct Workspace {
     uint32_t* out_vertices = nullptr;
     uint64_t out_vertices_cap = 0;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // traversal start, traversal end, finalize end
+    // When a call ends in BPT_ERANGE its sets stay in counts / where / pool;
+    // the retry with a larger buffer and the same arguments only re-runs the
+    // CSR assembly.  Any other call clears this.
+    bool have_last = false;
+    uint64_t last_first = 0, last_samples = 0, last_seed = 0;
+    uint32_t last_colors = 0;
+    bool last_unfused = false;
+    bpt_counters last_counters{};
 
     ~Workspace() {
         for (hipEvent_t e : ev)
@@ -130,9 +138,12 @@ namespace {
 
 bool valid_colors(uint32_t c) { return c == 64 || c == 128 || c == 256 || c == 512 || c == 1024; }
 
-// Fused workers: 4 workgroups of 256 threads per CU (a 128-thread shape with 8
-// per CU exists for tuning through BPT_FUSED_BLOCK; on the R-MAT workloads it
-// is slower: heavy batches need the lanes).
+// Fused workers.  Four 256-thread workgroups per CU, one batch each, when
+// memory allows that many slots.  When the graph is so large that the memory
+// budget allows fewer slots than that, two 512-thread workgroups per CU
+// instead, so that each batch gets more lanes and every SIMD still sees four
+// wavefronts (colour words up to 4).  128-thread workgroups (8 per CU) exist
+// for tuning through BPT_FUSED_BLOCK.
 constexpr int kMaxFusedPerCu = 8;
 
 int env_int(const char* name, int dflt) {
@@ -141,10 +152,11 @@ int env_int(const char* name, int dflt) {
     return atoi(v);
 }
 
-void fused_launch_shape(const bpt_graph* g, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
+void fused_launch_shape(const bpt_graph* g, int nw, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
     int bs = env_int("BPT_FUSED_BLOCK", 0);
-    if (bs != 128 && bs != 256) bs = 256;
-    const uint64_t resident = (uint64_t)g->cus * (bs == 128 ? 8 : 4);
+    if (bs != 128 && bs != 256 && !(bs == 512 && nw <= 4))
+        bs = (slots < (uint32_t)g->cus * 4 && nw <= 4) ? 512 : 256;
+    const uint64_t resident = (uint64_t)g->cus * (bs == 128 ? 8 : (bs == 256 ? 4 : 2));
     uint64_t gsz = std::min<uint64_t>({(uint64_t)slots, resident, n_batches});
     const int cap = env_int("BPT_FUSED_SLOTS", 0);
     if (cap > 0) gsz = std::min<uint64_t>(gsz, (uint64_t)cap);
@@ -245,6 +257,18 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
     return ws;
 }
 
+// Frees the graph's idle workspaces (all, or all but those of kind `keep_nw`).
+void trim_idle(bpt_graph* g, int keep_nw) {
+    std::vector<Workspace*> drop;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        std::vector<Workspace*> keep;
+        for (Workspace* ws : g->idle) (ws->nw == keep_nw ? keep : drop).push_back(ws);
+        g->idle.swap(keep);
+    }
+    for (Workspace* ws : drop) delete ws;
+}
+
 Workspace* acquire(bpt_graph* g, int nw) {
     {
         std::lock_guard<std::mutex> lk(g->mu);
@@ -256,7 +280,13 @@ Workspace* acquire(bpt_graph* g, int nw) {
             }
         }
     }
-    return make_workspace(g, nw);
+    try {
+        return make_workspace(g, nw);
+    } catch (const HipFail& f) {
+        if (f.status != BPT_ENOMEM) throw;
+        trim_idle(g, -1);  // out of device memory: drop cached workspaces of other kinds, retry once
+        return make_workspace(g, nw);
+    }
 }
 
 void release(bpt_graph* g, Workspace* ws) {
@@ -287,12 +317,21 @@ void ensure_sample_arrays(Workspace* ws, uint64_t n_samples) {
     }
 }
 
-void ensure_pool(Workspace* ws, uint64_t entries) {
+void ensure_pool(bpt_graph* g, Workspace* ws, uint64_t entries) {
     if (ws->pool_cap >= entries) return;
     dev_free(ws->pool);
+    dev_free(ws->out_vertices);
     ws->pool = nullptr;
     ws->pool_cap = 0;
-    ws->pool = dev_alloc<uint32_t>(entries);
+    ws->out_vertices = nullptr;
+    ws->out_vertices_cap = 0;
+    try {
+        ws->pool = dev_alloc<uint32_t>(entries);
+    } catch (const HipFail& f) {
+        if (f.status != BPT_ENOMEM) throw;
+        trim_idle(g, -1);
+        ws->pool = dev_alloc<uint32_t>(entries);
+    }
     ws->pool_cap = entries;
 }
 
@@ -329,10 +368,40 @@ void release_or_discard(bpt_graph* g, Workspace* ws, const CallResult& r) {
 int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32_t colors, uint64_t seed,
                  bool unfused, hipStream_t stream, unsigned long long* d_offsets, uint32_t* d_vertices,
                  uint64_t capacity, bool own_output, CallResult* res) {
+    const bool reuse = ws->have_last && ws->last_first == first && ws->last_samples == S &&
+                       ws->last_seed == seed && ws->last_colors == colors && ws->last_unfused == unfused;
+    if (reuse) {
+        if (own_output) {
+            ensure_out(ws, S, ws->pool_cap);
+            d_offsets = ws->out_offsets;
+            d_vertices = ws->out_vertices;
+            capacity = ws->out_vertices_cap;
+        }
+        HIP_TRY(hipEventRecord(ws->ev[1], stream));
+        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, ws->ctl,
+                                ws->scratch, ws->scratch_bytes, stream));
+        HIP_TRY(hipEventRecord(ws->ev[2], stream));
+        HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        float ms_fin = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms_fin, ws->ev[1], ws->ev[2]));
+        res->total = ws->ctl_host->total;
+        res->counters = ws->last_counters;
+        res->counters.traversal_ns = 0;  // no traversal ran
+        res->counters.finalize_ns = (uint64_t)((double)ms_fin * 1e6);
+        if (res->total > capacity) {
+            set_status(BPT_ERANGE, "output capacity " + std::to_string(capacity) + " < " +
+                                       std::to_string(res->total) + " members");
+            return BPT_ERANGE;
+        }
+        ws->have_last = false;  // delivered: the next call traverses again
+        return BPT_OK;
+    }
+    ws->have_last = false;
     ensure_sample_arrays(ws, S);
     if (ws->pool_cap == 0) {
         const uint64_t guess = std::max<uint64_t>(1u << 20, S * 32);
-        ensure_pool(ws, std::min<uint64_t>(guess, (uint64_t)g->n * S));
+        ensure_pool(g, ws, std::min<uint64_t>(guess, (uint64_t)g->n * S));
     }
     for (int attempt = 0; attempt < 8; ++attempt) {
         if (own_output) {
@@ -360,7 +429,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.colors = colors;
             a.n_batches = (S + colors - 1) / colors;
             int block = 256, grid = 1;
-            fused_launch_shape(g, ws->slots, a.n_batches, &block, &grid);
+            fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
         } else {
             UnfusedArgs a;
@@ -384,7 +453,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         const Control& c = *ws->ctl_host;
         if (c.err & kErrPoolOverflow) {
             const uint64_t need = c.pool_cursor + c.pool_cursor / 8 + 1024;
-            ensure_pool(ws, need);
+            ensure_pool(g, ws, need);
             continue;
         }
         if (c.err) {
@@ -410,6 +479,13 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         k.traversal_ns = (uint64_t)((double)ms_trav * 1e6);
         k.finalize_ns = (uint64_t)((double)ms_fin * 1e6);
         if (c.total > capacity) {
+            ws->have_last = true;  // keep the sets for the caller's retry
+            ws->last_first = first;
+            ws->last_samples = S;
+            ws->last_seed = seed;
+            ws->last_colors = colors;
+            ws->last_unfused = unfused;
+            ws->last_counters = k;
             set_status(BPT_ERANGE, "output capacity " + std::to_string(capacity) + " < " + std::to_string(c.total) +
                                        " members");
             return BPT_ERANGE;
@@ -671,6 +747,18 @@ int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_
     if (n) *n = gg->n;
     if (m) *m = gg->m;
     if (prob_layout) *prob_layout = gg->layout;
+    set_ok();
+    return BPT_OK;
+}
+
+int bpt_graph_release_cache(bpt_graph* g) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return BPT_EINVAL;
+    }
+    (void)hipSetDevice(gg->device);
+    trim_idle(gg, -1);
     set_ok();
     return BPT_OK;
 }

@@ -37,20 +37,22 @@ namespace bpt {
 namespace {
 
 constexpr int kWave = 64;
-// Workgroup size BS is a template parameter (128 or 256 threads); a chunk of
+// Workgroup size BS is a template parameter (128, 256 or 512 threads); a chunk of
 // BS frontier entries is staged per pass, and touched lists up to
 // sort_cap(BS) vertices are sorted in LDS.
 constexpr int sort_cap(int bs) { return bs >= 256 ? 4096 : 2048; }
+// Frontier entries each thread stages per pass (fewer for wide masks, to fit LDS).
+constexpr int ept(int nw) { return nw <= 2 ? 4 : (nw <= 4 ? 2 : 1); }
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
 
 template <int NW, int BS>
-struct Stage {  // traversal staging of one chunk of frontier entries
-    uint32_t beg[BS];
-    uint32_t end[BS];
-    uint32_t thr[BS];
-    uint32_t scan[BS];
-    unsigned long long mask[BS][NW];
+struct Stage {  // traversal staging of one chunk of ept(NW) * BS frontier entries
+    uint32_t beg[BS * ept(NW)];
+    uint32_t end[BS * ept(NW)];
+    uint32_t thr[BS * ept(NW)];
+    uint32_t scan[BS * ept(NW)];
+    unsigned long long mask[BS * ept(NW)][NW];
 };
 
 template <int NW, int BS>
@@ -427,18 +429,26 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
             const uint32_t tag = base_tag + level + 1;
             const uint32_t* qcur_arr = cur ? b.queue1 : b.queue0;
 
-            for (uint32_t c0 = 0; c0 < F; c0 += BS) {
-                const uint32_t cnt = min((uint32_t)BS, F - c0);
+            constexpr uint32_t kEPT = ept(NW);
+            constexpr uint32_t kChunk = BS * kEPT;
+            for (uint32_t c0 = 0; c0 < F; c0 += kChunk) {
+                const uint32_t cnt = min(kChunk, F - c0);
+                // thread tid stages entries [tid*kEPT, tid*kEPT + kEPT) of the chunk
+                uint32_t my_items[kEPT];
                 uint32_t items = 0;
-                if (tid < cnt) {
-                    const uint32_t v = qcur_arr[c0 + tid];
+#pragma unroll
+                for (uint32_t j = 0; j < kEPT; ++j) {
+                    const uint32_t e = tid * kEPT + j;
+                    my_items[j] = 0;
+                    if (e >= cnt) continue;
+                    const uint32_t v = qcur_arr[c0 + e];
                     const uint32_t beg = a.g.rowptr[v], end = a.g.rowptr[v + 1];
                     uint32_t pc = 0;
 #pragma unroll
                     for (int k = 0; k < NW; ++k) {
                         const unsigned long long mk =
                             atomicExch(&(cur ? b.frontier1 : b.frontier0)[(size_t)v * NW + k], 0ull);
-                        s.u.st.mask[tid][k] = mk;
+                        s.u.st.mask[e][k] = mk;
                         pc += (uint32_t)__popcll(mk);
                     }
                     uint32_t thr = 0;
@@ -447,19 +457,25 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
                     const uint32_t deg = end - beg;
                     const bool never = (layout != BPT_PROB_EDGE) && thr == 0;
                     const uint32_t quads = (deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
-                    items = (quads + kQuadsPerItem - 1) / kQuadsPerItem;
-                    s.u.st.beg[tid] = beg;
-                    s.u.st.end[tid] = end;
-                    s.u.st.thr[tid] = thr;
+                    my_items[j] = (quads + kQuadsPerItem - 1) / kQuadsPerItem;
+                    items += my_items[j];
+                    s.u.st.beg[e] = beg;
+                    s.u.st.end[e] = end;
+                    s.u.st.thr[e] = thr;
                     th_entries += 1;
                     th_ea += deg;
                     th_te += (unsigned long long)pc * deg;
                     th_members += pc;
                 }
                 uint32_t total;
-                const uint32_t excl = block_excl_scan<BS>(items, s.scan_tmp[scan_buf], &total);
+                uint32_t excl = block_excl_scan<BS>(items, s.scan_tmp[scan_buf], &total);
                 scan_buf ^= 1u;
-                if (tid < cnt) s.u.st.scan[tid] = excl;
+#pragma unroll
+                for (uint32_t j = 0; j < kEPT; ++j) {
+                    const uint32_t e = tid * kEPT + j;
+                    if (e < cnt) s.u.st.scan[e] = excl;
+                    excl += my_items[j];
+                }
                 __syncthreads();
 
                 // Heavy expansion levels are compute-bound while light ones wait on
@@ -477,7 +493,7 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
                                                 qnext, tag, base_tag, th_philox, th_live);
                 }
                 set_wave_priority(0);
-                if (c0 + BS < F) __syncthreads();  // the next chunk reuses the staging area
+                if (c0 + kChunk < F) __syncthreads();  // the next chunk reuses the staging area
             }
 
             ++level;
@@ -595,6 +611,13 @@ hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStre
             case 4: BPT_LAUNCH(4, 256); break;
             case 8: BPT_LAUNCH(8, 256); break;
             case 16: BPT_LAUNCH(16, 256); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (block == 512) {
+        switch (nw) {
+            case 1: BPT_LAUNCH(1, 512); break;
+            case 2: BPT_LAUNCH(2, 512); break;
+            case 4: BPT_LAUNCH(4, 512); break;
             default: return hipErrorInvalidValue;
         }
     } else {

@@ -161,9 +161,13 @@ def test_erange_and_repeatability(er_case):
     announce("ERANGE")
     st, total, _ = bpt.bpt_sample_rrr_device(g, 0, S, 64, 9, 0, None, off, vert, 8)
     assert st == bpt.BPT_ERANGE and total > 8
+    # the retry with a large enough buffer re-assembles the kept sets without traversing ...
     a = sample_device(g, 0, S, 64, 9)
+    assert a[2].traversal_ns == 0 and int(a[0][-1]) == total
+    # ... while every later call traverses again and returns the same sets
     for _ in range(3):
         b = sample_device(g, 0, S, 64, 9)
+        assert b[2].traversal_ns > 0
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
@@ -222,3 +226,22 @@ def test_hub_rows_split_across_workgroups(layout):
         assert cnt.sample_edges == int(ref.te.sum())
     off, ver, _ = sample_device(g, 0, S, 0, 23, flags=bpt.BPT_FLAG_UNFUSED)
     assert_same_sets(off, ver, ref, f"hub {layout} unfused")
+
+
+@pytest.mark.parametrize("block", ["128", "512"])
+def test_workgroup_shapes(block, monkeypatch):
+    """The 128- and 512-thread instantiations (chosen by the library for
+    small workspaces and for graphs whose slot memory is scarce) return the
+    same sets as the oracle, hub rows and every colour count included."""
+    n, src, dst = hub_graph()
+    prob = graphgen.wc_prob(n, dst)
+    og = oracle.Graph(n, src, dst, prob)
+    S = 2000
+    ref = og.sample(31, S, nthreads=8)
+    monkeypatch.setenv("BPT_FUSED_BLOCK", block)
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    for c in COLORS:
+        announce(f"hub graph block={block} C={c}")
+        off, ver, cnt = sample_device(g, 0, S, c, 31)
+        assert_same_sets(off, ver, ref, f"block={block} C={c}")
+        assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
