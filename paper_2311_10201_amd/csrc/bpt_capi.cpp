@@ -138,26 +138,29 @@ namespace {
 
 bool valid_colors(uint32_t c) { return c == 64 || c == 128 || c == 256 || c == 512 || c == 1024; }
 
-// Fused workers.  Four 256-thread workgroups per CU, one batch each, when
-// memory allows that many slots.  When the graph is so large that the memory
-// budget allows fewer slots than that, two 512-thread workgroups per CU
-// instead, so that each batch gets more lanes and every SIMD still sees four
-// wavefronts (colour words up to 4).  128-thread workgroups (8 per CU) exist
-// for tuning through BPT_FUSED_BLOCK.
-constexpr int kMaxFusedPerCu = 8;
-
 int env_int(const char* name, int dflt) {
     const char* v = getenv(name);
     if (!v || !*v) return dflt;
     return atoi(v);
 }
 
+// Fused workers: two 512-thread workgroups per CU, one batch each (four
+// wavefronts per SIMD), for masks of up to four words; four 256-thread
+// workgroups per CU for wider masks, whose LDS staging is larger.  A heavy
+// batch finishing alone on its CU keeps more lanes with the wider workgroup.
+// 128- and 1024-thread instantiations exist for tuning (BPT_FUSED_BLOCK).
+int fused_block(int nw) {
+    const int bs = env_int("BPT_FUSED_BLOCK", 0);
+    if (bs == 128 || bs == 256 || (bs == 512 && nw <= 4) || (bs == 1024 && nw == 1)) return bs;
+    return nw <= 4 ? 512 : 256;
+}
+
+// Workgroups of `bs` threads resident per CU (1024 threads per CU).
+uint64_t fused_per_cu(int bs) { return (uint64_t)(1024 / bs); }
+
 void fused_launch_shape(const bpt_graph* g, int nw, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
-    int bs = env_int("BPT_FUSED_BLOCK", 0);
-    if (bs != 128 && bs != 256 && !(bs == 512 && nw <= 4))
-        bs = (slots < (uint32_t)g->cus * 4 && nw <= 4) ? 512 : 256;
-    const uint64_t resident = (uint64_t)g->cus * (bs == 128 ? 8 : (bs == 256 ? 4 : 2));
-    uint64_t gsz = std::min<uint64_t>({(uint64_t)slots, resident, n_batches});
+    const int bs = fused_block(nw);
+    uint64_t gsz = std::min<uint64_t>({(uint64_t)slots, (uint64_t)g->cus * fused_per_cu(bs), n_batches});
     const int cap = env_int("BPT_FUSED_SLOTS", 0);
     if (cap > 0) gsz = std::min<uint64_t>(gsz, (uint64_t)cap);
     *block = bs;
@@ -207,7 +210,7 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
         char* p;
         if (nw > 0) {
             const size_t per = fused_slot_bytes(n, nw) + 1024;
-            size_t want = (size_t)g->cus * kMaxFusedPerCu;
+            size_t want = (size_t)(g->cus * fused_per_cu(fused_block(nw)));
             want = std::min(want, std::max<size_t>(1, budget / per));
             ws->slots = (uint32_t)std::max<size_t>(1, want);
             const size_t S = ws->slots, N = n;

@@ -120,6 +120,16 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, d, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, kWave);
+        x += ((unsigned long long)hi << 32) | lo;
+    }
+    return x;
+}
+
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long x, int src) {
     const uint32_t lo = __shfl((uint32_t)x, src, kWave);
     const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
@@ -228,48 +238,70 @@ __device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW, 
     }
 }
 
-// Coins of quads [q_first, q_end) of the row [beg, end) for every colour in
-// `mask`, and discovery of the live ones.
+__device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
+    return (coin_live(r.w0, t.x) ? 1u : 0u) | (coin_live(r.w1, t.y) ? 2u : 0u) | (coin_live(r.w2, t.z) ? 4u : 0u) |
+           (coin_live(r.w3, t.w) ? 8u : 0u);
+}
+
+// Coins of the work item's quads [q_first, q_end) (at most kQuadsPerItem) of
+// the row [beg, end) for every colour in `mask`, and discovery of the live
+// ones.  The item's Philox blocks of one colour are independent and are
+// evaluated side by side (all four when the mask is one word and any lane of
+// the wavefront has more than two quads, else in pairs), so that a wavefront
+// alone on its SIMD still keeps the multiplier pipeline busy.
 template <int NW, int BS>
-__device__ __forceinline__ void expand_quads(const FusedArgs& a, const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
-                                             const unsigned long long (&mask)[NW], unsigned long long s0,
-                                             uint32_t beg, uint32_t end, uint32_t thr_row, uint32_t q_first,
-                                             uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
-                                             uint32_t base_tag, unsigned long long& n_philox,
-                                             unsigned long long& n_live) {
+__device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
+                                            const unsigned long long (&mask)[NW], unsigned long long s0,
+                                            uint32_t beg, uint32_t end, uint32_t thr_row, uint32_t q_first,
+                                            uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
+                                            uint32_t base_tag, unsigned long long& n_philox,
+                                            unsigned long long& n_live) {
+    static_assert(kQuadsPerItem == 4, "an item's coin words must fit 16 bits");
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const uint32_t layout = a.g.prob_layout;
-    for (uint32_t quad = q_first; quad < q_end; ++quad) {
-        const uint32_t e0 = quad << 2;
-        uint32_t t0, t1, t2, t3;
-        if (layout == BPT_PROB_EDGE) {
-            const uint4 tt = *reinterpret_cast<const uint4*>(a.g.thr_edge + e0);
-            t0 = tt.x; t1 = tt.y; t2 = tt.z; t3 = tt.w;
-        } else {
-            t0 = t1 = t2 = t3 = thr_row;
-        }
-        // words of this quad that belong to the row
-        uint32_t valid = 0xFu;
-        if (e0 < beg) valid &= 0xFu << (beg - e0);
-        if (end - e0 < 4) valid &= (1u << (end - e0)) - 1u;
+    const uint32_t nq = q_end - q_first;
+    const uint32_t e_first = q_first << 2;
+    // coin words of the item that belong to the row
+    uint32_t valid = (end - e_first >= 16u) ? 0xFFFFu : ((1u << (end - e_first)) - 1u);
+    if (e_first < beg) valid &= 0xFFFFu << (beg - e_first);
+    const bool per_edge = a.g.prob_layout == BPT_PROB_EDGE;
+    const uint4 t_row = make_uint4(thr_row, thr_row, thr_row, thr_row);
+    // thresholds of quad j of the item (per-edge layout: re-read per colour, an L1 hit)
+    auto thr_of = [&](uint32_t j) -> uint4 {
+        return (per_edge && j < nq) ? *reinterpret_cast<const uint4*>(a.g.thr_edge + e_first + 4 * j) : t_row;
+    };
+    // four side by side only where registers allow it (one colour word); two otherwise
+    const bool wide = (NW == 1) && __any(nq > 2);
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            unsigned long long mk = mask[k];
-            while (mk) {
-                const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
-                mk &= mk - 1;
-                const uint32_t c = (uint32_t)k * 64u + bpos;
-                const Block4 r = coin_block(quad, s0 + c, k0, k1);
-                ++n_philox;
-                uint32_t live = (coin_live(r.w0, t0) ? 1u : 0u) | (coin_live(r.w1, t1) ? 2u : 0u) |
-                                (coin_live(r.w2, t2) ? 4u : 0u) | (coin_live(r.w3, t3) ? 8u : 0u);
-                live &= valid;
-                while (live) {
-                    const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
-                    live &= live - 1;
-                    ++n_live;
-                    discover<NW, BS>(b, s, a.g.col[e0 + j], c, nxt, qslot, tag, base_tag);
+    for (int k = 0; k < NW; ++k) {
+        unsigned long long mk = mask[k];
+        while (mk) {
+            const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
+            mk &= mk - 1;
+            const uint32_t c = (uint32_t)k * 64u + bpos;
+            const unsigned long long sc = s0 + c;
+            uint32_t live;
+            if (wide) {
+                const Block4 r0 = coin_block(q_first, sc, k0, k1);
+                const Block4 r1 = coin_block(q_first + 1, sc, k0, k1);
+                const Block4 r2 = coin_block(q_first + 2, sc, k0, k1);
+                const Block4 r3 = coin_block(q_first + 3, sc, k0, k1);
+                live = live_bits(r0, thr_of(0)) | (live_bits(r1, thr_of(1)) << 4) | (live_bits(r2, thr_of(2)) << 8) |
+                       (live_bits(r3, thr_of(3)) << 12);
+            } else {
+                live = 0;
+                for (uint32_t j = 0; j < nq; j += 2) {
+                    const Block4 r0 = coin_block(q_first + j, sc, k0, k1);
+                    const Block4 r1 = coin_block(q_first + j + 1, sc, k0, k1);  // past the row: masked below
+                    live |= (live_bits(r0, thr_of(j)) | (live_bits(r1, thr_of(j + 1)) << 4)) << (4 * j);
                 }
+            }
+            n_philox += nq;
+            live &= valid;
+            while (live) {
+                const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
+                live &= live - 1;
+                ++n_live;
+                discover<NW, BS>(b, s, a.g.col[e_first + j], c, nxt, qslot, tag, base_tag);
             }
         }
     }
@@ -363,7 +395,7 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
 }
 
 template <int NW, int BS>
-__global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fused_bpt_kernel(FusedArgs a) {
     __shared__ FusedShared<NW, BS> s;
     constexpr uint32_t kSortCap = sort_cap(BS);
     const uint32_t tid = threadIdx.x;
@@ -375,7 +407,7 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
 
     if (tid < kNumStats) s.stats[tid] = 0;
-    unsigned long long th_entries = 0, th_ea = 0, th_te = 0, th_philox = 0, th_live = 0, th_members = 0;
+    unsigned long long th_philox = 0, th_live = 0;
 
     for (;;) {
         __syncthreads();
@@ -436,6 +468,7 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
                 // thread tid stages entries [tid*kEPT, tid*kEPT + kEPT) of the chunk
                 uint32_t my_items[kEPT];
                 uint32_t items = 0;
+                unsigned long long ch_entries = 0, ch_ea = 0, ch_te = 0, ch_members = 0;
 #pragma unroll
                 for (uint32_t j = 0; j < kEPT; ++j) {
                     const uint32_t e = tid * kEPT + j;
@@ -462,10 +495,21 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
                     s.u.st.beg[e] = beg;
                     s.u.st.end[e] = end;
                     s.u.st.thr[e] = thr;
-                    th_entries += 1;
-                    th_ea += deg;
-                    th_te += (unsigned long long)pc * deg;
-                    th_members += pc;
+                    ch_entries += 1;
+                    ch_ea += deg;
+                    ch_te += (unsigned long long)pc * deg;
+                    ch_members += pc;
+                }
+                // the chunk's staging counters, one LDS update per wavefront
+                ch_entries = wave_sum64(ch_entries);
+                ch_ea = wave_sum64(ch_ea);
+                ch_te = wave_sum64(ch_te);
+                ch_members = wave_sum64(ch_members);
+                if (lane_id() == 0) {
+                    atomicAdd(&s.stats[kStatEntries], ch_entries);
+                    atomicAdd(&s.stats[kStatEdgeAccesses], ch_ea);
+                    atomicAdd(&s.stats[kStatSampleEdges], ch_te);
+                    atomicAdd(&s.stats[kStatMembers], ch_members);
                 }
                 uint32_t total;
                 uint32_t excl = block_excl_scan<BS>(items, s.scan_tmp[scan_buf], &total);
@@ -489,8 +533,8 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
                     unsigned long long mask[NW];
 #pragma unroll
                     for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
-                    expand_quads<NW, BS>(a, b, s, mask, s0, beg, end, s.u.st.thr[i], q_first, q_end, nxt,
-                                                qnext, tag, base_tag, th_philox, th_live);
+                    expand_item<NW, BS>(a, b, s, mask, s0, beg, end, s.u.st.thr[i], q_first, q_end, nxt, qnext, tag,
+                                        base_tag, th_philox, th_live);
                 }
                 set_wave_priority(0);
                 if (c0 + kChunk < F) __syncthreads();  // the next chunk reuses the staging area
@@ -577,12 +621,8 @@ __global__ __launch_bounds__(BS) void fused_bpt_kernel(FusedArgs a) {
     }
 
     // thread-local counters into the workgroup's totals, then the call's
-    atomicAdd(&s.stats[kStatEntries], th_entries);
-    atomicAdd(&s.stats[kStatEdgeAccesses], th_ea);
-    atomicAdd(&s.stats[kStatSampleEdges], th_te);
     atomicAdd(&s.stats[kStatPhilox], th_philox);
     atomicAdd(&s.stats[kStatLive], th_live);
-    atomicAdd(&s.stats[kStatMembers], th_members);
     __syncthreads();
     if (tid < kNumStats) {
         if (tid == kStatMaxLevels) atomicMax(&a.ctl->stats[tid], s.stats[tid]);
@@ -618,6 +658,11 @@ hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStre
             case 1: BPT_LAUNCH(1, 512); break;
             case 2: BPT_LAUNCH(2, 512); break;
             case 4: BPT_LAUNCH(4, 512); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (block == 1024) {
+        switch (nw) {
+            case 1: BPT_LAUNCH(1, 1024); break;
             default: return hipErrorInvalidValue;
         }
     } else {

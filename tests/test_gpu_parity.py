@@ -228,11 +228,11 @@ def test_hub_rows_split_across_workgroups(layout):
     assert_same_sets(off, ver, ref, f"hub {layout} unfused")
 
 
-@pytest.mark.parametrize("block", ["128", "512"])
+@pytest.mark.parametrize("block", ["128", "512", "1024"])
 def test_workgroup_shapes(block, monkeypatch):
-    """The 128- and 512-thread instantiations (chosen by the library for
-    small workspaces and for graphs whose slot memory is scarce) return the
-    same sets as the oracle, hub rows and every colour count included."""
+    """Every workgroup-size instantiation (128, 512 and 1024 threads besides
+    the default; sizes a colour count does not have fall back to it) returns
+    the oracle's sets, hub rows and every colour count included."""
     n, src, dst = hub_graph()
     prob = graphgen.wc_prob(n, dst)
     og = oracle.Graph(n, src, dst, prob)
