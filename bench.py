@@ -77,16 +77,16 @@ def make_graph(w):
     return n, src, dst, prob.astype(np.float32)
 
 
-def measured_traffic(workload: str, colors: int):
+def measured_traffic(workload: str, colors: int, workgroup_size: int):
     """HBM bytes per traversal launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel sources; else None."""
+    they were taken on the current kernel sources and launch shape; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     e = rec.get(f"{workload}/C{colors}")
-    if not e or e.get("kernel_digest") != kernel_digest():
+    if not e or e.get("kernel_digest") != kernel_digest() or e.get("workgroup_size") != workgroup_size:
         return None
     return e.get("bytes_per_launch")
 
@@ -245,16 +245,17 @@ def main() -> int:
         del host_res
 
     achieved = blocks / trav_s
-    traffic = measured_traffic(args.workload, colors)
+    traffic = measured_traffic(args.workload, colors, cnt.workgroup_size)
     roofline = {
         "bound": "alu",
-        "kernel": f"fused_bpt_kernel<{colors // 64}>",
+        "kernel": f"fused_bpt_kernel<{colors // 64}, {cnt.workgroup_size}>",
         "achieved": achieved / 1e9,
         "peak": PEAK_PHILOX_BLOCKS / 1e9,
         "unit": "G Philox4x32-10 blocks/s",
         "frac": achieved / PEAK_PHILOX_BLOCKS,
         "traffic": traffic,
         "per_launch": {"philox_blocks": blocks, "traversal_ms": trav_s * 1e3,
+                       "workgroup_size": cnt.workgroup_size, "workgroups": cnt.workgroups,
                        "kernel_digest": kernel_digest()},
     }
     hbm_bytes = None

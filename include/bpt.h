@@ -87,6 +87,8 @@ typedef struct bpt_counters {
     uint64_t traversal_ns;     /* duration of the traversal kernel (HIP events on the
                                   call's stream), nanoseconds                           */
     uint64_t finalize_ns;      /* duration of the CSR assembly kernels, nanoseconds     */
+    uint64_t workgroup_size;   /* threads per workgroup of the traversal launch         */
+    uint64_t workgroups;       /* workgroups of the traversal launch (persistent)       */
 } bpt_counters;
 
 /* ------------------------------------------------------------------------

@@ -53,7 +53,8 @@ EXPORTED_SYMBOLS = (
 class _Counters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "samples", "members", "sample_edges", "edge_accesses", "frontier_entries", "philox_blocks",
-        "live_coins", "levels", "max_levels", "batches", "traversal_ns", "finalize_ns")]
+        "live_coins", "levels", "max_levels", "batches", "traversal_ns", "finalize_ns", "workgroup_size",
+        "workgroups")]
 
 
 @dataclass
@@ -70,6 +71,8 @@ class Counters:
     batches: int = 0
     traversal_ns: int = 0
     finalize_ns: int = 0
+    workgroup_size: int = 0
+    workgroups: int = 0
 
 
 class BptError(RuntimeError):

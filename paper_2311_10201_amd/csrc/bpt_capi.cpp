@@ -415,6 +415,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         }
         HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), stream));
         HIP_TRY(hipEventRecord(ws->ev[0], stream));
+        int block = 256, grid = 1;
         Output out;
         out.counts = ws->counts;
         out.where = ws->where;
@@ -431,7 +432,6 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.n_samples = S;
             a.colors = colors;
             a.n_batches = (S + colors - 1) / colors;
-            int block = 256, grid = 1;
             fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
         } else {
@@ -444,7 +444,8 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.first_sample = first;
             a.n_samples = S;
             const uint64_t blocks_needed = (S + 3) / 4;
-            const int grid = (int)std::min<uint64_t>(ws->slots / 4, blocks_needed);
+            block = kUnfusedBlock;
+            grid = (int)std::min<uint64_t>(ws->slots / 4, blocks_needed);
             HIP_TRY(launch_unfused(a, grid, stream));
         }
         HIP_TRY(hipEventRecord(ws->ev[1], stream));
@@ -481,6 +482,8 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         HIP_TRY(hipEventElapsedTime(&ms_fin, ws->ev[1], ws->ev[2]));
         k.traversal_ns = (uint64_t)((double)ms_trav * 1e6);
         k.finalize_ns = (uint64_t)((double)ms_fin * 1e6);
+        k.workgroup_size = (uint64_t)block;
+        k.workgroups = (uint64_t)grid;
         if (c.total > capacity) {
             ws->have_last = true;  // keep the sets for the caller's retry
             ws->last_first = first;

@@ -27,6 +27,17 @@ def test_header_declarations_match_binding():
     assert declared_functions() == sorted(bpt.EXPORTED_SYMBOLS)
 
 
+def test_counters_struct_matches_header():
+    """The binding's bpt_counters mirrors the header's, field by field."""
+    with open(HEADER) as f:
+        text = f.read()
+    body = re.search(r"typedef struct bpt_counters \{(.*?)\} bpt_counters;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"uint64_t\s+(\w+);", body)
+    assert fields == [name for name, _ in bpt._Counters._fields_]
+    assert ctypes.sizeof(bpt._Counters) == 8 * len(fields)
+
+
 def test_library_exports_every_declared_symbol():
     lib = bpt.load_library()
     for name in declared_functions():
