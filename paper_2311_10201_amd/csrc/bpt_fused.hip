@@ -41,18 +41,21 @@ constexpr int kWave = 64;
 // BS frontier entries is staged per pass, and touched lists up to
 // sort_cap(BS) vertices are sorted in LDS.
 constexpr int sort_cap(int bs) { return bs >= 256 ? 4096 : 2048; }
-// Frontier entries each thread stages per pass (fewer for wide masks, to fit LDS).
-constexpr int ept(int nw) { return nw <= 2 ? 4 : (nw <= 4 ? 2 : 1); }
+// Frontier entries each thread stages per pass: fewer for wide masks and wide
+// workgroups, to fit LDS and to keep every instantiation within 128 VGPRs.
+constexpr int ept(int nw, int bs) {
+    return nw == 1 ? (bs <= 512 ? 4 : 2) : (nw == 2 ? (bs <= 256 ? 4 : 2) : (nw == 4 ? 2 : 1));
+}
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
 
 template <int NW, int BS>
-struct Stage {  // traversal staging of one chunk of ept(NW) * BS frontier entries
-    uint32_t beg[BS * ept(NW)];
-    uint32_t end[BS * ept(NW)];
-    uint32_t thr[BS * ept(NW)];
-    uint32_t scan[BS * ept(NW)];
-    unsigned long long mask[BS * ept(NW)][NW];
+struct Stage {  // traversal staging of one chunk of ept(NW, BS) * BS frontier entries
+    uint32_t beg[BS * ept(NW, BS)];
+    uint32_t end[BS * ept(NW, BS)];
+    uint32_t thr[BS * ept(NW, BS)];
+    uint32_t scan[BS * ept(NW, BS)];
+    unsigned long long mask[BS * ept(NW, BS)][NW];
 };
 
 template <int NW, int BS>
@@ -461,44 +464,63 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
             const uint32_t tag = base_tag + level + 1;
             const uint32_t* qcur_arr = cur ? b.queue1 : b.queue0;
 
-            constexpr uint32_t kEPT = ept(NW);
+            constexpr uint32_t kEPT = ept(NW, BS);
             constexpr uint32_t kChunk = BS * kEPT;
             for (uint32_t c0 = 0; c0 < F; c0 += kChunk) {
                 const uint32_t cnt = min(kChunk, F - c0);
-                // thread tid stages entries [tid*kEPT, tid*kEPT + kEPT) of the chunk
+                // Thread tid stages the chunk's queue entries tid, tid + BS, ... into LDS
+                // positions tid*kEPT + j (queue order carries no meaning), so a level
+                // smaller than the workgroup costs every thread at most one entry, and it
+                // issues all of their loads before using any result.
+                const uint32_t npos = min((uint32_t)BS, cnt) * kEPT;  // LDS positions in use
+                unsigned long long* fr_cur = cur ? b.frontier1 : b.frontier0;
+                uint32_t vq[kEPT];
+#pragma unroll
+                for (uint32_t j = 0; j < kEPT; ++j) {
+                    const uint32_t e = j * BS + tid;
+                    vq[j] = e < cnt ? qcur_arr[c0 + e] : 0u;
+                }
+                uint32_t rb[kEPT], re[kEPT], rt[kEPT];
+                unsigned long long mk[kEPT][NW];
+#pragma unroll
+                for (uint32_t j = 0; j < kEPT; ++j) {
+                    const bool ok = j * BS + tid < cnt;
+                    rb[j] = a.g.rowptr[vq[j]];
+                    re[j] = a.g.rowptr[vq[j] + 1];
+                    rt[j] = layout == BPT_PROB_ROW ? a.g.thr_row[vq[j]]
+                                                   : (layout == BPT_PROB_UNIFORM ? a.g.thr_uniform : 0u);
+#pragma unroll
+                    for (int k = 0; k < NW; ++k)
+                        mk[j][k] = ok ? atomicExch(&fr_cur[(size_t)vq[j] * NW + k], 0ull) : 0ull;
+                }
                 uint32_t my_items[kEPT];
                 uint32_t items = 0;
                 unsigned long long ch_entries = 0, ch_ea = 0, ch_te = 0, ch_members = 0;
 #pragma unroll
                 for (uint32_t j = 0; j < kEPT; ++j) {
-                    const uint32_t e = tid * kEPT + j;
-                    my_items[j] = 0;
-                    if (e >= cnt) continue;
-                    const uint32_t v = qcur_arr[c0 + e];
-                    const uint32_t beg = a.g.rowptr[v], end = a.g.rowptr[v + 1];
+                    const uint32_t pos = tid * kEPT + j;
+                    const bool ok = j * BS + tid < cnt;
                     uint32_t pc = 0;
 #pragma unroll
                     for (int k = 0; k < NW; ++k) {
-                        const unsigned long long mk =
-                            atomicExch(&(cur ? b.frontier1 : b.frontier0)[(size_t)v * NW + k], 0ull);
-                        s.u.st.mask[e][k] = mk;
-                        pc += (uint32_t)__popcll(mk);
+                        s.u.st.mask[pos][k] = mk[j][k];
+                        pc += (uint32_t)__popcll(mk[j][k]);
                     }
-                    uint32_t thr = 0;
-                    if (layout == BPT_PROB_ROW) thr = a.g.thr_row[v];
-                    else if (layout == BPT_PROB_UNIFORM) thr = a.g.thr_uniform;
-                    const uint32_t deg = end - beg;
-                    const bool never = (layout != BPT_PROB_EDGE) && thr == 0;
-                    const uint32_t quads = (deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
+                    const uint32_t beg = rb[j], end = re[j], deg = end - beg;
+                    const bool never = (layout != BPT_PROB_EDGE) && rt[j] == 0;
+                    const uint32_t quads =
+                        (!ok || deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
                     my_items[j] = (quads + kQuadsPerItem - 1) / kQuadsPerItem;
                     items += my_items[j];
-                    s.u.st.beg[e] = beg;
-                    s.u.st.end[e] = end;
-                    s.u.st.thr[e] = thr;
-                    ch_entries += 1;
-                    ch_ea += deg;
-                    ch_te += (unsigned long long)pc * deg;
-                    ch_members += pc;
+                    s.u.st.beg[pos] = beg;
+                    s.u.st.end[pos] = end;
+                    s.u.st.thr[pos] = rt[j];
+                    if (ok) {
+                        ch_entries += 1;
+                        ch_ea += deg;
+                        ch_te += (unsigned long long)pc * deg;
+                        ch_members += pc;
+                    }
                 }
                 // the chunk's staging counters, one LDS update per wavefront
                 ch_entries = wave_sum64(ch_entries);
@@ -516,8 +538,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                 scan_buf ^= 1u;
 #pragma unroll
                 for (uint32_t j = 0; j < kEPT; ++j) {
-                    const uint32_t e = tid * kEPT + j;
-                    if (e < cnt) s.u.st.scan[e] = excl;
+                    s.u.st.scan[tid * kEPT + j] = excl;
                     excl += my_items[j];
                 }
                 __syncthreads();
@@ -526,7 +547,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                 // memory: give the heavy ones issue priority on their SIMDs.
                 set_wave_priority(total >= 8u * BS ? 3 : (total >= 2u * BS ? 2 : (total >= BS / 2 ? 1 : 0)));
                 for (uint32_t t = tid; t < total; t += BS) {
-                    const uint32_t i = find_entry(s.u.st.scan, cnt, t);
+                    const uint32_t i = find_entry(s.u.st.scan, npos, t);
                     const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
                     const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * kQuadsPerItem;
                     const uint32_t q_end = min(q_first + kQuadsPerItem, ((end - 1) >> 2) + 1);
