@@ -91,6 +91,81 @@ def measured_traffic(workload: str, colors: int, workgroup_size: int):
     return e.get("bytes_per_launch")
 
 
+def fusion_study(out_path: str) -> int:
+    """Work saved by fusing and colour occupancy (the paper's synthetic analysis,
+    Section 4, Theorem 1 and its LFR figure) measured on the fused kernel's own
+    counters: LFR graphs with 10,000 vertices and average degree 4, 11, 16
+    (three graph seeds each), uniform traversal probability 0.01 ... 0.5,
+    10,240 random-start samples under three sample seeds, colours 8 ... 1024.
+
+      work ratio  = EA(C) / TE: edges the fused traversal scans over the edges
+                    C separate traversals scan (EA(1) = TE; Theorem 1: <= 1).
+      occupancy   = members / (C * frontier entries): the mean fraction of the
+                    batch's colours present in a frontier entry.
+    Both counters are checked against the oracle's level-synchronous
+    accounting by the GPU parity tests."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_10201_amd as bpt
+
+    n, S = 10_000, 10_240
+    degrees, graph_seeds = (4, 11, 16), (2, 3, 4)
+    probs, sample_seeds, colours = (0.01, 0.1, 0.2, 0.3, 0.4, 0.5), (1, 2, 3), (8, 16, 32, 64, 128, 256, 512, 1024)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    cap = n * S
+    vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+    rows, tuned = [], []
+    for deg in degrees:
+        for gs in graph_seeds:
+            src, dst = graphgen.lfr_graph(n, deg, gs)
+            for p in probs:
+                g = bpt.bpt_create_graph(n, src, dst, graphgen.uniform_prob(len(src), p))
+                for ss in sample_seeds:
+                    te = None
+                    for c in colours:
+                        st, total, cnt = bpt.bpt_sample_rrr_device(g, 0, S, c, ss, 0, stream, off, vert, cap)
+                        assert st == bpt.BPT_OK, st
+                        assert te is None or cnt.sample_edges == te  # TE does not depend on C
+                        te = cnt.sample_edges
+                        rows.append(dict(degree=deg, graph_seed=gs, m=len(src), p=p, seed=ss, colors=c,
+                                         sample_edges=cnt.sample_edges, edge_accesses=cnt.edge_accesses,
+                                         frontier_entries=cnt.frontier_entries, members=cnt.members,
+                                         traversal_ms=cnt.traversal_ns / 1e6))
+                tuned.append(dict(degree=deg, graph_seed=gs, p=p, colors=bpt.bpt_tune_colors(g, S, 1)))
+                bpt.bpt_free(g)
+            log(f"fusion study: degree {deg} graph seed {gs} done")
+    with open(out_path, "w") as f:
+        json.dump(dict(n=n, samples=S, rows=rows, tuned=tuned), f)
+
+    def mean(deg, p, c, fn):
+        xs = [fn(r) for r in rows if r["degree"] == deg and r["p"] == p and r["colors"] == c]
+        return sum(xs) / len(xs)
+
+    for title, fn in (("work ratio EA(C)/TE (%)", lambda r: 100 * r["edge_accesses"] / max(1, r["sample_edges"])),
+                      ("colour occupancy (%)", lambda r: 100 * r["members"] / max(1, r["colors"] * r["frontier_entries"]))):
+        print(f"\n{title}, mean over 3 graph seeds x 3 sample seeds\n")
+        print("| degree | p | " + " | ".join(f"C={c}" for c in colours) + " |")
+        print("|---|---|" + "---|" * len(colours))
+        for deg in degrees:
+            for p in probs:
+                print(f"| {deg} | {p} | " + " | ".join(f"{mean(deg, p, c, fn):.2f}" for c in colours) + " |")
+    print("\nfused traversal time (ms per launch of 10,240 samples), mean over the 9 runs; "
+          "autotuner's pick (bpt_tune_colors, sample seed 1) per graph seed\n")
+    print("| degree | p | " + " | ".join(f"C={c}" for c in colours) + " | fastest | tuner |")
+    print("|---|---|" + "---|" * (len(colours) + 2))
+    for deg in degrees:
+        for p in probs:
+            t = [mean(deg, p, c, lambda r: r["traversal_ms"]) for c in colours]
+            fastest = colours[min(range(len(t)), key=lambda i: t[i])]
+            picks = ",".join(str(x["colors"]) for x in tuned if x["degree"] == deg and x["p"] == p)
+            print(f"| {deg} | {p} | " + " | ".join(f"{x:.3f}" for x in t) + f" | {fastest} | {picks} |")
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +178,9 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (known bytes, for counter scaling)")
     ap.add_argument("--only", default="", help="time only this variant (fused64, fused256, unfused, ...)")
+    ap.add_argument("--fusion-study", default="", metavar="OUT.json",
+                    help="instead of the benchmark: edge accesses and colour occupancy of the fused traversal "
+                         "vs colour count and probability on LFR graphs; writes the records to OUT.json")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,6 +188,9 @@ def main() -> int:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sampling shards by sample-id range; see the design notes)", file=sys.stderr)
         return 2
+
+    if args.fusion_study:
+        return fusion_study(args.fusion_study)
 
     import numpy as np
     import torch

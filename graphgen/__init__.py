@@ -14,6 +14,9 @@ R-MAT graphs of the same order stand in for them):
                       distinct non-loop edges, drawn uniformly.
 * ``rmat_graph``    - R-MAT (recursive matrix) power-law graph; duplicates and
                       self-loops dropped.
+* ``lfr_graph``     - LFR benchmark graph (power-law degrees and community
+                      sizes; the paper's synthetic fusion analysis, Section 4),
+                      drawn by NetworkX, each undirected edge taken both ways.
 * ``uniform_prob``  - one fixed probability for every edge (the paper sweeps a
                       fixed traversal probability, Section 7).
 * ``wc_prob``       - weighted cascade: p(u->v) = 1/indeg(v) in fp32.
@@ -28,6 +31,7 @@ import numpy as np
 __all__ = [
     "er_graph",
     "rmat_graph",
+    "lfr_graph",
     "uniform_prob",
     "wc_prob",
     "edges_sha256",
@@ -104,6 +108,24 @@ def rmat_graph(scale: int, edge_factor: int, a: float, b: float, c: float,
     out_src = (key >> np.uint64(32)).astype(np.uint32)
     out_dst = (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)
     return out_src, out_dst
+
+
+def lfr_graph(n: int, average_degree: float, seed: int, tau1: float = 3.0, tau2: float = 1.5,
+              mu: float = 0.1, min_community: int = 20, max_community: int = 1000) -> tuple[np.ndarray, np.ndarray]:
+    """LFR benchmark graph (Lancichinetti, Fortunato, Radicchi 2008) as drawn by
+    NetworkX's ``LFR_benchmark_graph``: power-law degrees (exponent ``tau1``)
+    and community sizes (``tau2``), mixing ``mu``.  The graph is undirected;
+    every edge {u, v} becomes the two directed edges u->v and v->u, so each
+    vertex's out-degree is its LFR degree.  Sorted by (src, dst).  Not every
+    seed converges (NetworkX raises ExceededMaxIterations); seeds 2, 3 and 4
+    do for n = 10,000 at average degrees 4, 11 and 16."""
+    from networkx.generators.community import LFR_benchmark_graph
+    g = LFR_benchmark_graph(n, tau1, tau2, mu, average_degree=average_degree, min_community=min_community,
+                            max_community=max_community, seed=seed, max_iters=1000)
+    e = np.array(list(g.edges()), dtype=np.uint64).reshape(-1, 2)
+    e = e[e[:, 0] != e[:, 1]]
+    key = np.unique(np.concatenate([(e[:, 0] << np.uint64(32)) | e[:, 1], (e[:, 1] << np.uint64(32)) | e[:, 0]]))
+    return (key >> np.uint64(32)).astype(np.uint32), (key & np.uint64(0xFFFFFFFF)).astype(np.uint32)
 
 
 def uniform_prob(m: int, p: float) -> np.ndarray:

@@ -123,8 +123,10 @@ bpt_graph* bpt_create_graph(uint32_t n, uint64_t m, const uint32_t* src, const u
  *
  *   g                 graph from bpt_create_graph.
  *   n_samples         number of RRR sets, < 2^34.  0 gives an empty result.
- *   colors_per_batch  traversals fused per batch: 64, 128, 256, 512 or 1024;
- *                     0 lets the library choose.  Does not change the result.
+ *   colors_per_batch  traversals fused per batch: a power of two from 8 to
+ *                     1024 (below 64, a batch uses part of one 64-bit colour
+ *                     mask); 0 lets the library choose (bpt_default_colors).
+ *                     Does not change the result.
  *   seed              Philox key.
  *
  * Returns a host-resident CSR (see bpt_rrr_* accessors), or NULL on error:
@@ -196,8 +198,29 @@ int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_
 int bpt_graph_release_cache(bpt_graph* g);
 
 /* Colour count the library uses for colors_per_batch = 0 on this graph for a
- * job of n_samples samples (64 .. 1024). */
+ * job of n_samples samples: the one bpt_tune_colors measured for jobs of this
+ * size range, if any; otherwise the widest of 64, 32, 16, 8 that gives every
+ * workgroup the fused kernel keeps resident on this GPU at least one batch
+ * (a batch runs on one workgroup, and wider batches save row scans but no
+ * coin work).  0 for a bad handle. */
 uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples);
+
+/* ------------------------------------------------------------------------
+ * bpt_tune_colors - colour-count autotuner.  Times the fused traversal of
+ * sample ids 0 .. min(n_samples, 4 x 64 x resident workgroups) - 1 under
+ * `seed` at 8, 16, ..., 256 colours per batch (two runs each, HIP events,
+ * traversal plus CSR assembly) and remembers the fastest for this graph and
+ * jobs of the same power-of-two size range as n_samples: later calls with
+ * colors_per_batch = 0 (and bpt_default_colors) use it.  Which width is
+ * fastest depends on the graph and probabilities (dense sharing favours wide
+ * batches, small jobs narrow ones); the sets never do.
+ *
+ * Returns the chosen colour count, or 0 on error (bpt_last_status():
+ * BPT_EINVAL for a bad handle or n_samples outside [1, 2^34), or the errors
+ * of bpt_sample_rrr).  Runs traversals on the graph's device and returns no
+ * sets; safe to call concurrently with sampling calls on the same graph.
+ * ---------------------------------------------------------------------- */
+uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed);
 
 /* Host builds of the library's own arithmetic, for checks on machines
  * without a GPU: the threshold of an fp32 probability, the coin word of

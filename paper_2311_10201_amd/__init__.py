@@ -22,7 +22,7 @@ __all__ = [
     "BptError", "Counters", "Graph", "RRRResult",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_graph_info",
     "bpt_graph_release_cache",
-    "bpt_default_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
+    "bpt_default_colors", "bpt_tune_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
     "bpt_last_status", "bpt_last_error", "library_path", "load_library",
 ]
 
@@ -45,8 +45,8 @@ _lib = None
 EXPORTED_SYMBOLS = (
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_rrr_num_samples", "bpt_rrr_num_members",
     "bpt_rrr_offsets", "bpt_rrr_vertices", "bpt_last_status", "bpt_last_error", "bpt_sample_rrr_device",
-    "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_thr32", "bpt_coin_word",
-    "bpt_start_vertex", "bpt_version",
+    "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_tune_colors", "bpt_thr32",
+    "bpt_coin_word", "bpt_start_vertex", "bpt_version",
 )
 
 
@@ -116,6 +116,7 @@ def load_library():
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "bpt_graph_release_cache": (i32, [vp]),
         "bpt_default_colors": (u32, [vp, u64]),
+        "bpt_tune_colors": (u32, [vp, u64, u64]),
         "bpt_thr32": (u32, [ctypes.c_float]),
         "bpt_coin_word": (u32, [u64, u64, u64]),
         "bpt_start_vertex": (u32, [u64, u64, u32]),
@@ -271,7 +272,17 @@ def bpt_graph_release_cache(graph: Graph) -> None:
 
 
 def bpt_default_colors(graph: Graph, n_samples: int) -> int:
-    return int(load_library().bpt_default_colors(graph.handle, n_samples))
+    c = int(load_library().bpt_default_colors(graph.handle, n_samples))
+    if c == 0:
+        _raise_last()
+    return c
+
+
+def bpt_tune_colors(graph: Graph, n_samples: int, seed: int) -> int:
+    c = int(load_library().bpt_tune_colors(graph.handle, n_samples, seed))
+    if c == 0:
+        _raise_last()
+    return c
 
 
 def bpt_thr32(p: float) -> int:

@@ -123,6 +123,7 @@ struct bpt_graph {
     uint32_t* d_thr_edge;
     std::mutex mu;
     std::vector<bpt::Workspace*> idle;
+    uint32_t tuned[64] = {};  // colours measured fastest for jobs of 2^i .. 2^(i+1)-1 samples (0: none)
 };
 
 struct bpt_rrr {
@@ -136,7 +137,11 @@ struct bpt_rrr {
 namespace bpt {
 namespace {
 
-bool valid_colors(uint32_t c) { return c == 64 || c == 128 || c == 256 || c == 512 || c == 1024; }
+bool valid_colors(uint32_t c) { return c >= 8 && c <= 1024 && (c & (c - 1)) == 0; }
+
+// 64-bit mask words a batch of `colors` samples needs (batches below 64
+// colours use part of one word).
+int mask_words(uint32_t colors) { return (int)((colors + 63) / 64); }
 
 int env_int(const char* name, int dflt) {
     const char* v = getenv(name);
@@ -157,6 +162,15 @@ int fused_block(int nw) {
 
 // Workgroups of `bs` threads resident per CU (1024 threads per CU).
 uint64_t fused_per_cu(int bs) { return (uint64_t)(1024 / bs); }
+
+// Colour schedule of the fused expansion: chosen by the kernel, or forced
+// (BPT_GATHER=never|always, for tests and tuning; the sets are the same).
+uint32_t gather_mode() {
+    const char* v = getenv("BPT_GATHER");
+    if (v && !strcmp(v, "never")) return kGatherNever;
+    if (v && !strcmp(v, "always")) return kGatherAlways;
+    return kGatherAuto;
+}
 
 void fused_launch_shape(const bpt_graph* g, int nw, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
     const int bs = fused_block(nw);
@@ -432,6 +446,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.n_samples = S;
             a.colors = colors;
             a.n_batches = (S + colors - 1) / colors;
+            a.gather_mode = gather_mode();
             fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
         } else {
@@ -508,10 +523,25 @@ bpt_graph* check_graph(const void* h) {
     return g->magic == kGraphMagic ? const_cast<bpt_graph*>(g) : nullptr;
 }
 
-uint32_t choose_colors(const bpt_graph* g, uint64_t n_samples) {
-    (void)g;
-    (void)n_samples;
-    return 64;
+// Colours per batch when the caller leaves the choice to the library: the
+// width bpt_tune_colors measured fastest for jobs of this size, if any; else
+// the widest of 64, 32, 16, 8 colours that still gives every resident
+// workgroup a batch (coins are flipped per (edge, colour), so wider batches
+// save row scans but no Philox work, while a batch occupies one workgroup).
+int size_bucket(uint64_t n_samples) { return n_samples ? 63 - __builtin_clzll(n_samples) : 0; }
+
+uint64_t fused_resident(const bpt_graph* g) { return (uint64_t)g->cus * fused_per_cu(fused_block(1)); }
+
+uint32_t choose_colors(bpt_graph* g, uint64_t n_samples) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        const uint32_t t = g->tuned[size_bucket(n_samples)];
+        if (t) return t;
+    }
+    const uint64_t resident = fused_resident(g);
+    for (uint32_t c = 64; c > 8; c >>= 1)
+        if ((n_samples + c - 1) / c >= resident) return c;
+    return 8;
 }
 
 }  // namespace
@@ -596,7 +626,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
     if (!unfused) {
         if (colors == 0) colors = choose_colors(gg, n_samples);
         if (!valid_colors(colors)) {
-            set_status(BPT_EINVAL, "colors_per_batch must be 0, 64, 128, 256, 512 or 1024");
+            set_status(BPT_EINVAL, "colors_per_batch must be 0 or a power of two from 8 to 1024");
             return BPT_EINVAL;
         }
     }
@@ -616,7 +646,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
             set_ok();
             return BPT_OK;
         }
-        ws = acquire(gg, unfused ? 0 : (int)(colors / 64));
+        ws = acquire(gg, unfused ? 0 : mask_words(colors));
         CallResult res;
         const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, unfused, st,
                                     reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity, false,
@@ -648,7 +678,7 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
     }
     uint32_t colors = colors_per_batch == 0 ? choose_colors(gg, n_samples) : colors_per_batch;
     if (!valid_colors(colors)) {
-        set_status(BPT_EINVAL, "colors_per_batch must be 0, 64, 128, 256, 512 or 1024");
+        set_status(BPT_EINVAL, "colors_per_batch must be 0 or a power of two from 8 to 1024");
         return nullptr;
     }
     if (n_samples >= kMaxSamples) {
@@ -666,7 +696,7 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
         r->offsets[0] = 0;
         if (n_samples > 0) {
             HIP_TRY(hipSetDevice(gg->device));
-            ws = acquire(gg, (int)(colors / 64));
+            ws = acquire(gg, mask_words(colors));
             CallResult res;
             const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, false, nullptr, nullptr, nullptr, 0,
                                         true, &res);
@@ -770,8 +800,67 @@ int bpt_graph_release_cache(bpt_graph* g) {
 }
 
 uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples) {
-    const bpt_graph* gg = check_graph(g);
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return 0;
+    }
+    set_ok();
     return choose_colors(gg, n_samples);
+}
+
+uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return 0;
+    }
+    if (n_samples == 0 || n_samples >= kMaxSamples) {
+        set_status(BPT_EINVAL, "n_samples must be in [1, 2^34)");
+        return 0;
+    }
+    // Jobs beyond four 64-colour batches per resident workgroup behave alike
+    // per batch: the trial is capped there.
+    const uint64_t S = std::min<uint64_t>(n_samples, 4 * 64 * fused_resident(gg));
+    uint32_t best = 0;
+    uint64_t best_ns = ~0ull;
+    Workspace* ws = nullptr;
+    try {
+        HIP_TRY(hipSetDevice(gg->device));
+        for (uint32_t c = 8; c <= 256; c <<= 1) {
+            ws = acquire(gg, mask_words(c));
+            uint64_t ns = ~0ull;
+            for (int rep = 0; rep < 2; ++rep) {  // the first run also loads the kernel
+                CallResult res;
+                const int rc = run_sampling(gg, ws, 0, S, c, seed, false, nullptr, nullptr, nullptr, 0, true, &res);
+                if (rc != BPT_OK) {
+                    release_or_discard(gg, ws, res);
+                    return 0;  // status set by run_sampling
+                }
+                ns = std::min<uint64_t>(ns, res.counters.traversal_ns + res.counters.finalize_ns);
+            }
+            release(gg, ws);
+            ws = nullptr;
+            if (ns < best_ns) {
+                best_ns = ns;
+                best = c;
+            }
+        }
+    } catch (const HipFail& f) {
+        if (ws) release(gg, ws);
+        set_status(f.status, f.msg);
+        return 0;
+    } catch (const std::bad_alloc&) {
+        if (ws) release(gg, ws);
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return 0;
+    }
+    {
+        std::lock_guard<std::mutex> lk(gg->mu);
+        gg->tuned[size_bucket(n_samples)] = best;
+    }
+    set_ok();
+    return best;
 }
 
 uint32_t bpt_thr32(float p) { return threshold_of(p); }

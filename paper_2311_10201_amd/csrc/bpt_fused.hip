@@ -44,7 +44,7 @@ constexpr int sort_cap(int bs) { return bs >= 256 ? 4096 : 2048; }
 // Frontier entries each thread stages per pass: fewer for wide masks and wide
 // workgroups, to fit LDS and to keep every instantiation within 128 VGPRs.
 constexpr int ept(int nw, int bs) {
-    return nw == 1 ? (bs <= 512 ? 4 : 2) : (nw == 2 ? (bs <= 256 ? 4 : 2) : (nw == 4 ? 2 : 1));
+    return nw == 1 ? (bs <= 512 ? 4 : 2) : (nw == 2 ? (bs <= 256 ? 4 : 2) : (nw == 4 && bs <= 256 ? 2 : 1));
 }
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
@@ -202,20 +202,22 @@ __device__ __forceinline__ BatchCtx<NW> slot_ctx(const FusedArgs& a, uint32_t sl
     return b;
 }
 
-// (u, c) became reachable: record it once (Listing 1's visited / frontier
-// update, with the visited mark taken at discovery time).  `next` is the
+// Colours `bits` of word k reached u over live edges: record the new ones once
+// (Listing 1's visited / frontier update, one atomic per mask word as in its
+// fusing OR, with the visited mark taken at discovery time).  `next` is the
 // parity of the level the new frontier entry belongs to, `qslot` its counter.
 template <int NW, int BS>
-__device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW, BS>& s, uint32_t u, uint32_t c,
-                                         int next, uint32_t qslot, uint32_t tag, uint32_t base_tag) {
-    const uint32_t w = c >> 6;
-    const unsigned long long bit = 1ull << (c & 63);
-    const size_t idx = (size_t)u * NW + w;
-    const unsigned long long old = atomicOr(&b.visited[idx], bit);
-    if (old & bit) return;
-    atomicAdd(&s.cnt[c], 1u);
+__device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, FusedShared<NW, BS>& s, uint32_t u, int k,
+                                              unsigned long long bits, int next, uint32_t qslot, uint32_t tag,
+                                              uint32_t base_tag) {
+    const size_t idx = (size_t)u * NW + k;
+    const unsigned long long old = atomicOr(&b.visited[idx], bits);
+    unsigned long long fresh = bits & ~old;
+    if (!fresh) return;
     unsigned long long* fr = next ? b.frontier1 : b.frontier0;
-    const unsigned long long old_next = atomicOr(&fr[idx], bit);
+    const unsigned long long old_next = atomicOr(&fr[idx], fresh);
+    for (unsigned long long f = fresh; f; f &= f - 1)
+        atomicAdd(&s.cnt[k * 64 + (__ffsll((long long)f) - 1)], 1u);
     bool push, first;
     if constexpr (NW == 1) {
         (void)tag;
@@ -241,6 +243,13 @@ __device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW, 
     }
 }
 
+// (u, c) became reachable (one colour).
+template <int NW, int BS>
+__device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW, BS>& s, uint32_t u, uint32_t c,
+                                         int next, uint32_t qslot, uint32_t tag, uint32_t base_tag) {
+    discover_word<NW, BS>(b, s, u, (int)(c >> 6), 1ull << (c & 63), next, qslot, tag, base_tag);
+}
+
 __device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
     return (coin_live(r.w0, t.x) ? 1u : 0u) | (coin_live(r.w1, t.y) ? 2u : 0u) | (coin_live(r.w2, t.z) ? 4u : 0u) |
            (coin_live(r.w3, t.w) ? 8u : 0u);
@@ -248,10 +257,16 @@ __device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
 
 // Coins of the work item's quads [q_first, q_end) (at most kQuadsPerItem) of
 // the row [beg, end) for every colour in `mask`, and discovery of the live
-// ones.  The item's Philox blocks of one colour are independent and are
-// evaluated side by side (all four when the mask is one word and any lane of
-// the wavefront has more than two quads, else in pairs), so that a wavefront
-// alone on its SIMD still keeps the multiplier pipeline busy.
+// ones.  Two schedules, chosen per wavefront (FusedArgs::gather_mode):
+//  * mostly one colour per entry: the item's Philox blocks of a colour are
+//    independent and are evaluated side by side (all four when the mask is one
+//    word and any lane has more than two quads, else in pairs), so that a
+//    wavefront alone on its SIMD still keeps the multiplier pipeline busy;
+//    each live coin is discovered on its own;
+//  * several colours per entry: per (quad, mask word) the blocks of two
+//    colours are evaluated side by side and each edge's live colours are
+//    gathered into one mask, so visited[u] and the next frontier take one
+//    atomic per (edge, word) whatever the number of colours (Listing 1).
 template <int NW, int BS>
 __device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
                                             const unsigned long long (&mask)[NW], unsigned long long s0,
@@ -272,6 +287,56 @@ __device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<N
     auto thr_of = [&](uint32_t j) -> uint4 {
         return (per_edge && j < nq) ? *reinterpret_cast<const uint4*>(a.g.thr_edge + e_first + 4 * j) : t_row;
     };
+    // Gathering pays when an edge is expected to be live for several colours at
+    // once: colours of the entry x probability >= 1/2 (per-edge thresholds
+    // count as 1/2).  A wavefront gathers when a quarter of its lanes would.
+    uint32_t pc = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) pc += (uint32_t)__popcll(mask[k]);
+    const uint32_t p_est = per_edge ? 0x80000000u : thr_row;
+    const bool want = pc >= 2 && (unsigned long long)pc * p_est >= 0x80000000ull;
+    const bool gather = a.gather_mode == kGatherAlways ||
+                        (a.gather_mode == kGatherAuto &&
+                         4 * __popcll(__ballot(want)) >= (unsigned)__popcll(__ballot(true)));
+
+    if (gather) {
+        for (uint32_t j = 0; j < nq; ++j) {
+            const uint32_t quad = q_first + j;
+            const uint4 t = thr_of(j);
+            const uint32_t vq = (valid >> (4 * j)) & 0xFu;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                unsigned long long mk = mask[k];
+                unsigned long long acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;  // live colours of the 4 edges
+                while (mk) {
+                    // two colours side by side; an absent second one repeats b0 and is dropped
+                    const uint32_t b0 = (uint32_t)(__ffsll((long long)mk) - 1);
+                    mk &= mk - 1;
+                    const bool h1 = mk != 0;
+                    const uint32_t b1 = h1 ? (uint32_t)(__ffsll((long long)mk) - 1) : b0;
+                    mk &= h1 ? mk - 1 : mk;
+                    const unsigned long long sk = s0 + (unsigned long long)k * 64u;
+                    const Block4 r0 = coin_block(quad, sk + b0, k0, k1);
+                    const Block4 r1 = coin_block(quad, sk + b1, k0, k1);
+                    n_philox += h1 ? 2u : 1u;
+                    const uint32_t l0 = live_bits(r0, t) & vq;
+                    const uint32_t l1 = h1 ? live_bits(r1, t) & vq : 0u;
+                    const unsigned long long m0 = 1ull << b0, m1 = 1ull << b1;
+                    acc0 |= ((l0 & 1u) ? m0 : 0ull) | ((l1 & 1u) ? m1 : 0ull);
+                    acc1 |= ((l0 & 2u) ? m0 : 0ull) | ((l1 & 2u) ? m1 : 0ull);
+                    acc2 |= ((l0 & 4u) ? m0 : 0ull) | ((l1 & 4u) ? m1 : 0ull);
+                    acc3 |= ((l0 & 8u) ? m0 : 0ull) | ((l1 & 8u) ? m1 : 0ull);
+                }
+                const uint32_t e0 = quad << 2;
+                if (acc0) { n_live += __popcll(acc0); discover_word<NW, BS>(b, s, a.g.col[e0], k, acc0, nxt, qslot, tag, base_tag); }
+                if (acc1) { n_live += __popcll(acc1); discover_word<NW, BS>(b, s, a.g.col[e0 + 1], k, acc1, nxt, qslot, tag, base_tag); }
+                if (acc2) { n_live += __popcll(acc2); discover_word<NW, BS>(b, s, a.g.col[e0 + 2], k, acc2, nxt, qslot, tag, base_tag); }
+                if (acc3) { n_live += __popcll(acc3); discover_word<NW, BS>(b, s, a.g.col[e0 + 3], k, acc3, nxt, qslot, tag, base_tag); }
+            }
+        }
+        return;
+    }
+
     // four side by side only where registers allow it (one colour word); two otherwise
     const bool wide = (NW == 1) && __any(nq > 2);
 #pragma unroll
@@ -420,8 +485,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         __syncthreads();
         const uint64_t batch = s.batch;
         if (batch >= a.n_batches) break;
-        const uint64_t s0 = a.first_sample + batch * C;
-        const uint32_t ncol = (uint32_t)min((uint64_t)C, a.n_samples - batch * C);
+        // samples s0 .. s0 + ncol - 1 take colours 0 .. ncol - 1 (a.colors <= C per batch)
+        const uint64_t s0 = a.first_sample + batch * a.colors;
+        const uint32_t ncol = (uint32_t)min((uint64_t)a.colors, a.n_samples - batch * a.colors);
 
         uint32_t base_tag = 0;
         if constexpr (NW > 1) {

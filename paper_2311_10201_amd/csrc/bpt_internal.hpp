@@ -83,7 +83,12 @@ struct FusedArgs {
     uint64_t n_samples;
     uint64_t n_batches;
     uint32_t colors;
+    uint32_t gather_mode;  // kGatherAuto, kGatherNever or kGatherAlways
 };
+
+// How the fused expansion schedules an entry's colours (see expand_item):
+// chosen per wavefront from the expected live colours per edge, or forced.
+enum GatherMode : uint32_t { kGatherAuto = 0, kGatherNever = 1, kGatherAlways = 2 };
 
 // Per-wave state of the unfused traversal.
 struct UnfusedSlots {

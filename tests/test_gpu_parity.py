@@ -15,7 +15,7 @@ from gpu_util import announce, assert_same_sets, sample_device
 
 pytestmark = pytest.mark.gpu
 
-COLORS = [64, 128, 256, 512, 1024]
+COLORS = [8, 16, 32, 64, 128, 256, 512, 1024]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "er1000_m10000_p0.1_seed42.txt")
 
 
@@ -174,12 +174,54 @@ def test_erange_and_repeatability(er_case):
 def test_invalid_sampling_arguments(er_case):
     n, src, dst, prob = er_case
     g = bpt.bpt_create_graph(n, src, dst, prob)
-    for c in (1, 32, 96, 2048):
+    for c in (1, 4, 24, 96, 2048):
         with pytest.raises(bpt.BptError) as ei:
             bpt.bpt_sample_rrr(g, 10, c, 1)
         assert ei.value.status == bpt.BPT_EINVAL
     with pytest.raises(bpt.BptError):
         bpt.bpt_sample_rrr(g, 1 << 34, 64, 1)
+
+
+def test_default_colors_fill_the_gpu(er_case):
+    """colors_per_batch = 0: 64 colours when there are batches for every
+    resident workgroup, narrower batches for small jobs; the sets equal the
+    oracle's either way."""
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    assert bpt.bpt_default_colors(g, 10_000_000) == 64
+    assert bpt.bpt_default_colors(g, 100) == 8
+    widths = [bpt.bpt_default_colors(g, s) for s in (100, 3_000, 10_000, 30_000, 100_000, 1_000_000)]
+    assert widths == sorted(widths) and set(widths) <= {8, 16, 32, 64}
+    S = 3000
+    ref = oracle.Graph(n, src, dst, prob).sample(5, S, nthreads=8)
+    announce(f"default colours S={S}: {bpt.bpt_default_colors(g, S)}")
+    off, ver, cnt = sample_device(g, 0, S, 0, 5)
+    assert_same_sets(off, ver, ref, "default colours")
+    c = bpt.bpt_default_colors(g, S)
+    assert cnt.batches == (S + c - 1) // c
+
+
+def test_tuned_colors_are_remembered(er_case):
+    """bpt_tune_colors measures the widths and the chosen one becomes the
+    default for jobs of that size range on that graph only; the sets stay the
+    oracle's."""
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    other = bpt.bpt_create_graph(n, src, dst, prob)
+    before = bpt.bpt_default_colors(other, 3000)
+    announce("tune colours S=3000")
+    c = bpt.bpt_tune_colors(g, 3000, 5)
+    assert c in (8, 16, 32, 64, 128, 256)
+    assert bpt.bpt_default_colors(g, 3000) == c
+    assert bpt.bpt_default_colors(g, 2048) == c and bpt.bpt_default_colors(g, 4095) == c
+    assert bpt.bpt_default_colors(other, 3000) == before
+    S = 2500
+    ref = oracle.Graph(n, src, dst, prob).sample(11, S, nthreads=8)
+    off, ver, cnt = sample_device(g, 0, S, 0, 11)
+    assert_same_sets(off, ver, ref, "tuned colours")
+    assert cnt.batches == (S + c - 1) // c
+    with pytest.raises(bpt.BptError):
+        bpt.bpt_tune_colors(g, 0, 5)
 
 
 def hub_graph(n=20_000, hubs=12, hub_in=9_000, hub_out=1_500, m_rand=60_000, seed=17):
@@ -245,3 +287,29 @@ def test_workgroup_shapes(block, monkeypatch):
         off, ver, cnt = sample_device(g, 0, S, c, 31)
         assert_same_sets(off, ver, ref, f"block={block} C={c}")
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+
+
+@pytest.mark.parametrize("mode", ["never", "always"])
+@pytest.mark.parametrize("layout", ["uniform", "edge"])
+def test_colour_schedules(mode, layout, monkeypatch):
+    """Both colour schedules of the fused expansion (one atomic per live coin,
+    or live colours gathered per edge into one mask atomic) return the
+    oracle's sets and edge-access counts, at a probability where entries carry
+    many colours."""
+    n, src, dst = hub_graph(n=6_000, hubs=6, hub_in=5_000, hub_out=800, m_rand=30_000, seed=29)
+    if layout == "uniform":
+        prob = graphgen.uniform_prob(len(src), 0.2)
+    else:
+        prob = (np.random.Generator(np.random.PCG64(4)).random(len(src), dtype=np.float32)
+                * np.float32(0.4)).astype(np.float32)
+    og = oracle.Graph(n, src, dst, prob)
+    S = 1500
+    ref = og.sample(37, S, nthreads=8)
+    monkeypatch.setenv("BPT_GATHER", mode)
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    for c in COLORS:
+        announce(f"colour schedule {mode} layout={layout} C={c}")
+        off, ver, cnt = sample_device(g, 0, S, c, 37)
+        assert_same_sets(off, ver, ref, f"{mode} {layout} C={c}")
+        assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+        assert cnt.live_coins <= cnt.philox_blocks * 4
