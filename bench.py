@@ -32,6 +32,12 @@ WORKLOADS = {
     # R-MAT scale 22, edge factor 16, uniform p = 0.01, 1,000,000 samples
     "rmat22-p0.01": dict(kind="rmat", scale=22, ef=16, a=0.57, b=0.19, c=0.19, graph_seed=22, prob=0.01,
                          samples=1_000_000, seed=42, colors=(64, 256), cpu_stride=401),
+    # 32 uneven R-MAT instances (scale 12-21, edge factor 8/16/32, uniform p 0.01/0.05/0.1 or weighted
+    # cascade, 1k-200k samples, log-uniform), all sampled by one bpt_sample_rrr_jobs call; each
+    # instance's sample count is capped so its sets hold at most 2^27 vertex ids
+    "rmat-mix32": dict(kind="mix", instances=32, draw_seed=2311, scale_lo=12, scale_hi=21, efs=(8, 16, 32),
+                       probs=(0.01, 0.05, 0.1, "wc"), samples_lo=1_000, samples_hi=200_000, out_budget=1 << 27,
+                       check_per_instance=16),
     # Erdos-Renyi n = 1,000, m = 10,000, p = 0.1, 64 samples
     "er1000-p0.1": dict(kind="er", n=1000, m=10_000, graph_seed=42, prob=0.1, samples=64, seed=42, colors=(64,),
                         cpu_stride=1),
@@ -92,9 +98,9 @@ def measured_traffic(workload: str, colors: int, workgroup_size: int):
 
 
 def fusion_study(out_path: str) -> int:
-    """Work saved by fusing and colour occupancy (the paper's synthetic analysis,
-    Section 4, Theorem 1 and its LFR figure) measured on the fused kernel's own
-    counters: LFR graphs with 10,000 vertices and average degree 4, 11, 16
+    """Work saved by fusing and colour occupancy (the paper's synthetic analysis
+    of Section 3.2 with its LFR figure, and Theorem 1 of Section 3.1) measured
+    on the fused kernel's own counters: LFR graphs with 10,000 vertices and average degree 4, 11, 16
     (three graph seeds each), uniform traversal probability 0.01 ... 0.5,
     10,240 random-start samples under three sample seeds, colours 8 ... 1024.
 
@@ -166,6 +172,157 @@ def fusion_study(out_path: str) -> int:
     return 0
 
 
+def mix_instances(w):
+    """The seeded draw of the mix's instances (shapes only; graphs come later)."""
+    import math
+
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(w["draw_seed"]))
+    out = []
+    for i in range(w["instances"]):
+        scale = int(rng.integers(w["scale_lo"], w["scale_hi"] + 1))
+        ef = int(rng.choice(np.array(w["efs"])))
+        prob = w["probs"][int(rng.integers(len(w["probs"])))]
+        samples = int(round(math.exp(rng.uniform(math.log(w["samples_lo"]), math.log(w["samples_hi"])))))
+        out.append(dict(scale=scale, ef=ef, prob=prob, samples=samples, graph_seed=1000 + i, seed=42 + i))
+    return out
+
+
+def bench_mix(args, w) -> int:
+    """Many uneven sampling jobs: one bpt_sample_rrr_jobs call (one persistent
+    fused launch per mask width) against one bpt_sample_rrr_device call per
+    instance, on the same GPU and buffers."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_10201_amd as bpt
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    insts = mix_instances(w)
+    t0 = time.perf_counter()
+    for k in insts:
+        src, dst = graphgen.rmat_graph(k["scale"], k["ef"], 0.57, 0.19, 0.19, seed=k["graph_seed"])
+        n = 1 << k["scale"]
+        prob = graphgen.wc_prob(n, dst) if k["prob"] == "wc" else graphgen.uniform_prob(len(src), k["prob"])
+        k.update(n=n, m=len(src), src=src, dst=dst, p=prob, g=bpt.bpt_create_graph(n, src, dst, prob))
+    log(f"mix: {len(insts)} graphs generated and built in {time.perf_counter() - t0:.1f}s")
+
+    def device_run(k, S, cap):
+        off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+        vert = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        st, total, cnt = bpt.bpt_sample_rrr_device(k["g"], 0, S, k.get("colors", 0), k["seed"], 0, stream, off,
+                                                   vert, cap)
+        return st, total, cnt, off, vert
+
+    # output budget from a 256-sample pilot (the sets' mean size)
+    for k in insts:
+        cap = 1 << 20
+        st, total, _, _, _ = device_run(k, 256, cap)
+        if st == bpt.BPT_ERANGE:
+            st, total, _, _, _ = device_run(k, 256, total)
+        mean = max(1.0, total / 256)
+        k["samples"] = int(max(64, min(k["samples"], w["out_budget"] // int(np.ceil(mean)))))
+        # colours when sampled alone: measured by the autotuner, or the library's rule
+        k["colors"] = (bpt.bpt_tune_colors(k["g"], k["samples"], k["seed"]) if args.tune
+                       else bpt.bpt_default_colors(k["g"], k["samples"]))
+    S_all = sum(k["samples"] for k in insts)
+    log(f"mix: {S_all} samples in all; colours {[k['colors'] for k in insts]}")
+
+    # reference outputs: one call per instance (exact buffer sizes)
+    for k in insts:
+        st, total, cnt, off, vert = device_run(k, k["samples"], 1 << 20)
+        if st == bpt.BPT_ERANGE:
+            st, total, cnt, off, vert = device_run(k, k["samples"], total)
+        assert st == bpt.BPT_OK
+        k.update(total=total, off_ref=off, vert_ref=vert)
+    jobs = [bpt.Job(k["g"], 0, k["samples"], k["seed"], torch.empty(k["samples"] + 1, dtype=torch.int64, device="cuda"),
+                    torch.empty(max(k["total"], 1), dtype=torch.int32, device="cuda"), k["total"], k["colors"])
+            for k in insts]
+    st, cnt = bpt.bpt_sample_rrr_jobs(jobs, stream)
+    assert st == bpt.BPT_OK
+    same = all(j.total == k["total"] and torch.equal(j.d_offsets, k["off_ref"]) and
+               torch.equal(j.d_vertices[:j.total], k["vert_ref"][:k["total"]]) for j, k in zip(jobs, insts))
+    log(f"mix: one launch == per-instance calls on all {S_all} sets: {same}")
+
+    def time_batched():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, c = bpt.bpt_sample_rrr_jobs(jobs, stream)
+        torch.cuda.synchronize()
+        assert st == bpt.BPT_OK
+        return time.perf_counter() - t, c
+
+    def time_sequential():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k, j in zip(insts, jobs):
+            st, _, _ = bpt.bpt_sample_rrr_device(k["g"], 0, k["samples"], k["colors"], k["seed"], 0, stream,
+                                                 j.d_offsets, j.d_vertices, j.capacity)
+            assert st == bpt.BPT_OK
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    for _ in range(max(1, args.warmup)):
+        time_batched()
+        time_sequential()
+    bt, cnts = zip(*[time_batched() for _ in range(args.steps)])
+    sq = [time_sequential() for _ in range(args.steps)]
+    sec, sec_seq = sum(bt) / len(bt), sum(sq) / len(sq)
+    cnt = cnts[-1]
+    trav_s = sum(c.traversal_ns for c in cnts) / len(cnts) / 1e9
+    achieved = cnt.philox_blocks / trav_s
+    result = {
+        "metric": "RRR samples/sec over a 32-instance R-MAT mix: one multi-job fused launch vs one call per "
+                  "instance (bit-exact)",
+        "value": S_all / sec, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": args.workload, "instances": len(insts), "samples": S_all,
+                   "members": int(cnt.members),
+                   "mix": [dict(scale=k["scale"], ef=k["ef"], prob=k["prob"], m=k["m"], samples=k["samples"],
+                                colors=k["colors"]) for k in insts],
+                   "colors": "bpt_tune_colors per instance" if args.tune else "the library's rule per instance"},
+        "edges_per_s": cnt.sample_edges / sec,
+        "sequential": {"samples_per_s": S_all / sec_seq, "ms_per_step": sec_seq * 1e3},
+        "speedup_vs_sequential": sec_seq / sec,
+        "roofline": {"bound": "alu", "kernel": "fused_bpt_kernel (all mask widths of the mix)",
+                     "achieved": achieved / 1e9, "peak": PEAK_PHILOX_BLOCKS / 1e9,
+                     "unit": "G Philox4x32-10 blocks/s", "frac": achieved / PEAK_PHILOX_BLOCKS, "traffic": None,
+                     "per_launch": {"philox_blocks": cnt.philox_blocks, "traversal_ms": trav_s * 1e3}},
+        "parity": None,
+    }
+    log(f"mix: batched {sec * 1e3:.2f} ms, sequential {sec_seq * 1e3:.2f} ms")
+
+    ok = same
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        cpu_s, n_cpu, te = 0.0, 0, 0
+        for k, j in zip(insts, jobs):
+            ids = np.unique(np.linspace(0, k["samples"] - 1, w["check_per_instance"]).astype(np.uint64))
+            og = oracle.Graph(k["n"], k["src"], k["dst"], k["p"])
+            t = time.perf_counter()
+            ref = og.sample_ids(k["seed"], ids, nthreads=threads)
+            cpu_s += time.perf_counter() - t
+            n_cpu += len(ids)
+            te += int(ref.te.sum())
+            off = j.d_offsets.cpu().numpy().view(np.uint64)
+            for i, s_id in enumerate(ids.tolist()):
+                got = j.d_vertices[int(off[s_id]):int(off[s_id + 1])].cpu().numpy().view(np.uint32)
+                ok = ok and np.array_equal(got, ref.set_of(i))
+        result["cpu_baseline"] = {"value": n_cpu / cpu_s, "unit": "samples/s", "cores": threads, "kind": "oracle",
+                                  "sample": f"{n_cpu} sample ids spread over the {len(insts)} instances "
+                                            "(oracle time only, graph builds excluded)",
+                                  "edges_per_s": te / cpu_s}
+        result["parity"] = (f"one launch == per-instance calls on all {S_all} sets; bit-exact vs oracle on "
+                            f"{n_cpu} sampled sets" if ok else "MISMATCH")
+        log(f"mix: oracle parity {'ok' if ok else 'FAILED'}")
+    print(json.dumps(result), flush=True)
+    return 0 if ok else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +335,8 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (known bytes, for counter scaling)")
     ap.add_argument("--only", default="", help="time only this variant (fused64, fused256, unfused, ...)")
+    ap.add_argument("--tune", action="store_true",
+                    help="rmat-mix32: choose each instance's colours with bpt_tune_colors (untimed)")
     ap.add_argument("--fusion-study", default="", metavar="OUT.json",
                     help="instead of the benchmark: edge accesses and colour occupancy of the fused traversal "
                          "vs colour count and probability on LFR graphs; writes the records to OUT.json")
@@ -198,6 +357,8 @@ def main() -> int:
     import paper_2311_10201_amd as bpt
 
     w = WORKLOADS[args.workload]
+    if w["kind"] == "mix":
+        return bench_mix(args, w)
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")

@@ -15,7 +15,7 @@ R-MAT graphs of the same order stand in for them):
 * ``rmat_graph``    - R-MAT (recursive matrix) power-law graph; duplicates and
                       self-loops dropped.
 * ``lfr_graph``     - LFR benchmark graph (power-law degrees and community
-                      sizes; the paper's synthetic fusion analysis, Section 4),
+                      sizes; the paper's synthetic fusion analysis, Section 3.2),
                       drawn by NetworkX, each undirected edge taken both ways.
 * ``uniform_prob``  - one fixed probability for every edge (the paper sweeps a
                       fixed traversal probability, Section 7).

@@ -117,6 +117,22 @@ typedef struct bpt_counters {
 bpt_graph* bpt_create_graph(uint32_t n, uint64_t m, const uint32_t* src, const uint32_t* dst,
                             const float* prob);
 
+/* One request of bpt_sample_rrr_jobs(). */
+typedef struct bpt_job {
+    bpt_graph* graph;          /* in: graph; all jobs of a call on one device          */
+    uint64_t first_sample;     /* in: first sample id                                  */
+    uint64_t n_samples;        /* in: sets wanted (ids first_sample .. + n_samples - 1) */
+    uint64_t seed;             /* in: Philox key                                       */
+    uint32_t colors_per_batch; /* in: as in bpt_sample_rrr (0: library's choice)       */
+    uint32_t reserved;         /* in: must be 0                                        */
+    uint64_t* d_offsets;       /* in: device array of n_samples + 1 entries            */
+    uint32_t* d_vertices;      /* in: device array of `capacity` entries               */
+    uint64_t capacity;         /* in                                                   */
+    uint64_t total;            /* out: members of the job's sets                       */
+    int32_t status;            /* out: BPT_OK, or BPT_ERANGE when capacity < total     */
+    uint32_t reserved2;        /* in: must be 0                                        */
+} bpt_job;
+
 /* ------------------------------------------------------------------------
  * bpt_sample_rrr - sample RRR sets 0 .. n_samples-1 with fused BPTs
  * (paper Section 3, Listing 1) and return them in host memory.
@@ -196,6 +212,35 @@ int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_
  * vertices).  Calls in flight on other threads keep theirs.  The next sampling
  * call allocates again.  Returns BPT_OK or BPT_EINVAL. */
 int bpt_graph_release_cache(bpt_graph* g);
+
+/* ------------------------------------------------------------------------
+ * bpt_sample_rrr_jobs - many sampling requests, possibly on different graphs,
+ * in one persistent fused launch (paper Section 4.1: one thread block runs a
+ * group of fused traversals, and many groups are in flight).  The batches of all jobs form one list that the
+ * launch's workgroups claim from a device counter, so small jobs share the GPU
+ * instead of each under-filling it; then every job's CSR is written to its own
+ * d_offsets / d_vertices exactly as bpt_sample_rrr_device would write it for
+ * the same graph, sample range, seed and colours (the sets do not depend on
+ * what else is in the launch).  A job's colors_per_batch of 0 is settled as
+ * for the job alone (bpt_default_colors): a job whose samples are few, or
+ * heavy, then still splits into many batches.  Jobs may use different colour
+ * counts: jobs
+ * whose batches need the same number of 64-bit mask words share a launch
+ * (so at most five launches, widest masks first).
+ *
+ *   jobs, n_jobs  the requests; `total` and `status` are written back.
+ *   stream        hipStream_t for all work (NULL: default stream); the call
+ *                 returns after the stream has finished it.
+ *   counters      if not NULL: totals over all jobs (bpt_counters above;
+ *                 times summed over the launches, the launch shape the
+ *                 largest).
+ *
+ * Returns BPT_OK; BPT_ERANGE when some job's capacity is below its total
+ * (that job's d_offsets and total are valid, its d_vertices untouched; the
+ * other jobs' outputs are complete); BPT_EINVAL for a bad job (nothing runs);
+ * or BPT_ENOMEM, BPT_EDEVICE, BPT_EINTERNAL.
+ * ---------------------------------------------------------------------- */
+int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counters* counters);
 
 /* Colour count the library uses for colors_per_batch = 0 on this graph for a
  * job of n_samples samples: the one bpt_tune_colors measured for jobs of this

@@ -19,8 +19,9 @@ import numpy as np
 __all__ = [
     "BPT_OK", "BPT_EINVAL", "BPT_ENOMEM", "BPT_EDEVICE", "BPT_ERANGE", "BPT_EINTERNAL",
     "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED",
-    "BptError", "Counters", "Graph", "RRRResult",
-    "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_graph_info",
+    "BptError", "Counters", "Graph", "Job", "RRRResult",
+    "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
+    "bpt_graph_info",
     "bpt_graph_release_cache",
     "bpt_default_colors", "bpt_tune_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
     "bpt_last_status", "bpt_last_error", "library_path", "load_library",
@@ -46,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_rrr_num_samples", "bpt_rrr_num_members",
     "bpt_rrr_offsets", "bpt_rrr_vertices", "bpt_last_status", "bpt_last_error", "bpt_sample_rrr_device",
     "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_tune_colors", "bpt_thr32",
-    "bpt_coin_word", "bpt_start_vertex", "bpt_version",
+    "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs",
 )
 
 
@@ -55,6 +56,28 @@ class _Counters(ctypes.Structure):
         "samples", "members", "sample_edges", "edge_accesses", "frontier_entries", "philox_blocks",
         "live_coins", "levels", "max_levels", "batches", "traversal_ns", "finalize_ns", "workgroup_size",
         "workgroups")]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("first_sample", ctypes.c_uint64), ("n_samples", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("colors_per_batch", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("d_offsets", ctypes.c_void_p), ("d_vertices", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("total", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved2", ctypes.c_uint32)]
+
+
+@dataclass
+class Job:
+    """One request of bpt_sample_rrr_jobs (device buffers: torch tensors or addresses)."""
+    graph: "Graph"
+    first_sample: int
+    n_samples: int
+    seed: int
+    d_offsets: object
+    d_vertices: object
+    capacity: int
+    colors_per_batch: int = 0
+    total: int = 0
+    status: int = BPT_OK
 
 
 @dataclass
@@ -113,6 +136,7 @@ def load_library():
         "bpt_last_error": (cp, []),
         "bpt_sample_rrr_device": (i32, [vp, u64, u64, u32, u64, u32, vp, vp, vp, u64,
                                         ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
+        "bpt_sample_rrr_jobs": (i32, [ctypes.POINTER(_Job), u32, vp, ctypes.POINTER(_Counters)]),
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "bpt_graph_release_cache": (i32, [vp]),
         "bpt_default_colors": (u32, [vp, u64]),
@@ -256,6 +280,25 @@ def bpt_sample_rrr_device(graph: Graph, first_sample: int, n_samples: int, color
     if st not in (BPT_OK, BPT_ERANGE):
         _raise_last()
     return st, int(total.value), Counters(**{k: int(getattr(cnt, k)) for k, _ in _Counters._fields_})
+
+
+def bpt_sample_rrr_jobs(jobs, stream=None):
+    """Runs all jobs in one fused launch; fills each Job's total and status.
+    Returns (status, Counters); status is BPT_OK or BPT_ERANGE (some job's
+    capacity below its total)."""
+    lib = load_library()
+    arr = (_Job * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        arr[i] = _Job(j.graph.handle, j.first_sample, j.n_samples, j.seed, j.colors_per_batch, 0,
+                      _addr(j.d_offsets), _addr(j.d_vertices), j.capacity, 0, 0, 0)
+    cnt = _Counters()
+    st = lib.bpt_sample_rrr_jobs(arr, len(jobs), _stream(stream), ctypes.byref(cnt))
+    if st not in (BPT_OK, BPT_ERANGE):
+        _raise_last()
+    for i, j in enumerate(jobs):
+        j.total = int(arr[i].total)
+        j.status = int(arr[i].status)
+    return st, Counters(**{k: int(getattr(cnt, k)) for k, _ in _Counters._fields_})
 
 
 def bpt_graph_info(graph: Graph):

@@ -65,6 +65,7 @@ void dev_free(void* p) {
 struct Workspace {
     int nw = 0;  // colour words per mask (fused), 0 = unfused
     uint32_t slots = 0;
+    bool full = false;  // as many slots as a launch on this device can use (or memory allows)
     void* slot_mem = nullptr;
     FusedSlots fs{};
     UnfusedSlots us{};
@@ -81,6 +82,12 @@ struct Workspace {
     uint64_t out_offsets_cap = 0;
     uint32_t* out_vertices = nullptr;
     uint64_t out_vertices_cap = 0;
+    // job table of multi-job launches: device copy, pinned host staging, totals
+    FusedJob* d_jobs = nullptr;
+    FusedJob* h_jobs = nullptr;
+    unsigned long long* d_totals = nullptr;
+    unsigned long long* h_totals = nullptr;
+    uint32_t jobs_cap = 0;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // traversal start, traversal end, finalize end
     // When a call ends in BPT_ERANGE its sets stay in counts / where / pool;
     // the retry with a larger buffer and the same arguments only re-runs the
@@ -103,6 +110,10 @@ struct Workspace {
         dev_free(scratch);
         dev_free(out_offsets);
         dev_free(out_vertices);
+        dev_free(d_jobs);
+        dev_free(d_totals);
+        if (h_jobs) (void)hipHostFree(h_jobs);
+        if (h_totals) (void)hipHostFree(h_totals);
     }
 };
 
@@ -215,7 +226,17 @@ size_t memory_budget() {
 }
 
 // Allocates and zeroes the traversal state of a new workspace.
-Workspace* make_workspace(bpt_graph* g, int nw) {
+// Traversal slots a job of `units` batches (fused) or samples (unfused) can
+// keep busy at once, rounded up to a power of two so that workspaces are
+// reused across jobs of similar size.
+uint64_t slots_wanted(const bpt_graph* g, int nw, uint64_t units) {
+    const uint64_t cap = nw > 0 ? (uint64_t)g->cus * fused_per_cu(fused_block(nw)) : (uint64_t)g->cus * 16;
+    uint64_t want = 1;
+    while (want < units && want < cap) want <<= 1;
+    return std::min(want, cap);
+}
+
+Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
     Workspace* ws = new Workspace();
     ws->nw = nw;
     try {
@@ -224,9 +245,11 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
         char* p;
         if (nw > 0) {
             const size_t per = fused_slot_bytes(n, nw) + 1024;
-            size_t want = (size_t)(g->cus * fused_per_cu(fused_block(nw)));
-            want = std::min(want, std::max<size_t>(1, budget / per));
+            const size_t device_max = (size_t)(g->cus * fused_per_cu(fused_block(nw)));
+            const size_t mem_max = std::max<size_t>(1, budget / per);
+            const size_t want = std::min<size_t>(slots_wanted(g, nw, units), mem_max);
             ws->slots = (uint32_t)std::max<size_t>(1, want);
+            ws->full = want >= device_max || want >= mem_max;
             const size_t S = ws->slots, N = n;
             const size_t words = bitmap_words(n);
             size_t bytes = S * per + S * 4 + 4096;
@@ -248,10 +271,12 @@ Workspace* make_workspace(bpt_graph* g, int nw) {
             ws->fs.slots = ws->slots;
         } else {
             const size_t per = unfused_slot_bytes(n) + 512;
-            size_t want = (size_t)g->cus * 16;  // wavefronts
-            want = std::min(want, std::max<size_t>(4, budget / per));
+            const size_t device_max = (size_t)g->cus * 16;  // wavefronts
+            const size_t mem_max = std::max<size_t>(4, budget / per);
+            size_t want = std::min<size_t>(slots_wanted(g, 0, units), mem_max);
             want = std::max<size_t>(4, want / 4 * 4);  // whole workgroups of 4 waves
             ws->slots = (uint32_t)want;
+            ws->full = want >= device_max || want + 4 > mem_max;
             const size_t S = ws->slots;
             const size_t words = bitmap_words(n);
             size_t bytes = S * per + 1024;
@@ -286,23 +311,32 @@ void trim_idle(bpt_graph* g, int keep_nw) {
     for (Workspace* ws : drop) delete ws;
 }
 
-Workspace* acquire(bpt_graph* g, int nw) {
+// A workspace of kind `nw` for a job of `units` batches (fused) or samples
+// (unfused): an idle one with enough slots, else a new one sized to the job
+// (smaller idle ones of the same kind are then dropped).
+Workspace* acquire(bpt_graph* g, int nw, uint64_t units) {
+    const uint64_t want = slots_wanted(g, nw, units);
+    std::vector<Workspace*> drop;
     {
         std::lock_guard<std::mutex> lk(g->mu);
         for (size_t i = 0; i < g->idle.size(); ++i) {
-            if (g->idle[i]->nw == nw) {
-                Workspace* ws = g->idle[i];
+            Workspace* ws = g->idle[i];
+            if (ws->nw == nw && (ws->slots >= want || ws->full)) {
                 g->idle.erase(g->idle.begin() + i);
                 return ws;
             }
         }
+        std::vector<Workspace*> keep;
+        for (Workspace* ws : g->idle) (ws->nw == nw ? drop : keep).push_back(ws);
+        g->idle.swap(keep);
     }
+    for (Workspace* ws : drop) delete ws;
     try {
-        return make_workspace(g, nw);
+        return make_workspace(g, nw, units);
     } catch (const HipFail& f) {
         if (f.status != BPT_ENOMEM) throw;
         trim_idle(g, -1);  // out of device memory: drop cached workspaces of other kinds, retry once
-        return make_workspace(g, nw);
+        return make_workspace(g, nw, units);
     }
 }
 
@@ -369,6 +403,26 @@ void ensure_out(Workspace* ws, uint64_t n_samples, uint64_t entries) {
     }
 }
 
+void ensure_jobs(Workspace* ws, uint32_t n_jobs) {
+    if (ws->jobs_cap >= n_jobs) return;
+    dev_free(ws->d_jobs);
+    dev_free(ws->d_totals);
+    if (ws->h_jobs) (void)hipHostFree(ws->h_jobs);
+    if (ws->h_totals) (void)hipHostFree(ws->h_totals);
+    ws->d_jobs = nullptr;
+    ws->d_totals = nullptr;
+    ws->h_jobs = nullptr;
+    ws->h_totals = nullptr;
+    ws->jobs_cap = 0;
+    const uint32_t cap = std::max<uint32_t>(n_jobs, 64);
+    ws->d_jobs = dev_alloc<FusedJob>(cap);
+    ws->d_totals = dev_alloc<unsigned long long>(cap);
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ws->h_jobs), cap * sizeof(FusedJob), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ws->h_totals), cap * sizeof(unsigned long long),
+                          hipHostMallocDefault));
+    ws->jobs_cap = cap;
+}
+
 struct CallResult {
     uint64_t total = 0;
     bpt_counters counters{};
@@ -395,7 +449,8 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             capacity = ws->out_vertices_cap;
         }
         HIP_TRY(hipEventRecord(ws->ev[1], stream));
-        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, ws->ctl,
+        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, &ws->ctl->total,
+                                &ws->ctl->err,
                                 ws->scratch, ws->scratch_bytes, stream));
         HIP_TRY(hipEventRecord(ws->ev[2], stream));
         HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream));
@@ -436,15 +491,20 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         out.pool = ws->pool;
         out.pool_cap = ws->pool_cap;
         if (!unfused) {
-            FusedArgs a;
-            a.g = dev_graph(g);
+            FusedArgs a = {};
+            a.job0.g = dev_graph(g);
+            a.job0.seed = seed;
+            a.job0.first_sample = first;
+            a.job0.n_samples = S;
+            a.job0.batch_begin = 0;
+            a.job0.out_base = 0;
+            a.job0.colors = colors;
+            a.jobs = nullptr;
+            a.n_jobs = 1;
+            a.n_max = g->n;
             a.ws = ws->fs;
             a.out = out;
             a.ctl = ws->ctl;
-            a.seed = seed;
-            a.first_sample = first;
-            a.n_samples = S;
-            a.colors = colors;
             a.n_batches = (S + colors - 1) / colors;
             a.gather_mode = gather_mode();
             fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
@@ -464,7 +524,8 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             HIP_TRY(launch_unfused(a, grid, stream));
         }
         HIP_TRY(hipEventRecord(ws->ev[1], stream));
-        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, ws->ctl,
+        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, S, d_offsets, d_vertices, capacity, &ws->ctl->total,
+                                &ws->ctl->err,
                                 ws->scratch, ws->scratch_bytes, stream));
         HIP_TRY(hipEventRecord(ws->ev[2], stream));
         HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream));
@@ -521,6 +582,108 @@ bpt_graph* check_graph(const void* h) {
     if (!h) return nullptr;
     const bpt_graph* g = static_cast<const bpt_graph*>(h);
     return g->magic == kGraphMagic ? const_cast<bpt_graph*>(g) : nullptr;
+}
+
+// One fused launch over several jobs (bpt_sample_rrr_jobs): the batches of
+// all jobs form one list that the persistent workgroups claim from a device
+// counter; each job's sets are then assembled into its own buffers.  `owner`
+// is the job graph with the most vertices: its workspace's slots are large
+// enough for every job.  Jobs with no samples are not in `live`.
+int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<uint32_t>& live,
+             const std::vector<uint32_t>& colors, hipStream_t stream, bpt_counters* counters) {
+    const uint32_t J = (uint32_t)live.size();
+    ensure_jobs(ws, J);
+    uint64_t n_batches = 0, total_samples = 0;
+    for (uint32_t i = 0; i < J; ++i) {
+        const bpt_job& jb = jobs[live[i]];
+        FusedJob& fj = ws->h_jobs[i];
+        fj = FusedJob{};
+        fj.g = dev_graph(jb.graph);
+        fj.seed = jb.seed;
+        fj.first_sample = jb.first_sample;
+        fj.n_samples = jb.n_samples;
+        fj.batch_begin = n_batches;
+        fj.out_base = total_samples;
+        fj.colors = colors[live[i]];
+        n_batches += (jb.n_samples + fj.colors - 1) / fj.colors;
+        total_samples += jb.n_samples;
+    }
+    ensure_sample_arrays(ws, total_samples);
+    if (ws->pool_cap == 0) ensure_pool(owner, ws, std::max<uint64_t>(1u << 20, total_samples * 32));
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), stream));
+        HIP_TRY(hipMemcpyAsync(ws->d_jobs, ws->h_jobs, J * sizeof(FusedJob), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipEventRecord(ws->ev[0], stream));
+        FusedArgs a = {};
+        a.jobs = ws->d_jobs;
+        a.n_jobs = J;
+        a.n_max = owner->n;
+        a.ws = ws->fs;
+        a.out.counts = ws->counts;
+        a.out.where = ws->where;
+        a.out.pool = ws->pool;
+        a.out.pool_cap = ws->pool_cap;
+        a.ctl = ws->ctl;
+        a.n_batches = n_batches;
+        a.gather_mode = gather_mode();
+        int block = 256, grid = 1;
+        fused_launch_shape(owner, ws->nw, ws->slots, n_batches, &block, &grid);
+        HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
+        HIP_TRY(hipEventRecord(ws->ev[1], stream));
+        for (uint32_t i = 0; i < J; ++i) {
+            const bpt_job& jb = jobs[live[i]];
+            const uint64_t base = ws->h_jobs[i].out_base;
+            HIP_TRY(launch_finalize(ws->counts + base, ws->where + base, ws->pool, jb.n_samples,
+                                    reinterpret_cast<unsigned long long*>(jb.d_offsets), jb.d_vertices, jb.capacity,
+                                    ws->d_totals + i, &ws->ctl->err, ws->scratch, ws->scratch_bytes, stream));
+        }
+        HIP_TRY(hipEventRecord(ws->ev[2], stream));
+        HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(ws->h_totals, ws->d_totals, J * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const Control& c = *ws->ctl_host;
+        if (c.err & kErrPoolOverflow) {
+            ensure_pool(owner, ws, c.pool_cursor + c.pool_cursor / 8 + 1024);
+            continue;
+        }
+        if (c.err) {
+            set_status(BPT_EINTERNAL, "device consistency check failed (error bits " + std::to_string(c.err) + ")");
+            return BPT_EINTERNAL;
+        }
+        int rc = BPT_OK;
+        for (uint32_t i = 0; i < J; ++i) {
+            bpt_job& jb = jobs[live[i]];
+            jb.total = ws->h_totals[i];
+            jb.status = jb.total > jb.capacity ? BPT_ERANGE : BPT_OK;
+            if (jb.status != BPT_OK) rc = BPT_ERANGE;
+        }
+        if (counters) {
+            bpt_counters& k = *counters;
+            k = bpt_counters{};
+            k.samples = total_samples;
+            k.members = c.stats[kStatMembers];
+            k.sample_edges = c.stats[kStatSampleEdges];
+            k.edge_accesses = c.stats[kStatEdgeAccesses];
+            k.frontier_entries = c.stats[kStatEntries];
+            k.philox_blocks = c.stats[kStatPhilox];
+            k.live_coins = c.stats[kStatLive];
+            k.levels = c.stats[kStatLevels];
+            k.max_levels = c.stats[kStatMaxLevels];
+            k.batches = c.stats[kStatBatches];
+            float ms_trav = 0.f, ms_fin = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms_trav, ws->ev[0], ws->ev[1]));
+            HIP_TRY(hipEventElapsedTime(&ms_fin, ws->ev[1], ws->ev[2]));
+            k.traversal_ns = (uint64_t)((double)ms_trav * 1e6);
+            k.finalize_ns = (uint64_t)((double)ms_fin * 1e6);
+            k.workgroup_size = (uint64_t)block;
+            k.workgroups = (uint64_t)grid;
+        }
+        if (rc != BPT_OK) set_status(rc, "a job's output capacity is below its total (see the job's total)");
+        return rc;
+    }
+    set_status(BPT_ENOMEM, "output pool kept overflowing");
+    return BPT_ENOMEM;
 }
 
 // Colours per batch when the caller leaves the choice to the library: the
@@ -646,7 +809,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
             set_ok();
             return BPT_OK;
         }
-        ws = acquire(gg, unfused ? 0 : mask_words(colors));
+        ws = acquire(gg, unfused ? 0 : mask_words(colors), unfused ? n_samples : (n_samples + colors - 1) / colors);
         CallResult res;
         const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, unfused, st,
                                     reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity, false,
@@ -665,6 +828,135 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
         return f.status;
     } catch (const std::bad_alloc&) {
         if (ws) release(gg, ws);
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return BPT_ENOMEM;
+    }
+}
+
+int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counters* counters) {
+    if (n_jobs > 0 && !jobs) {
+        set_status(BPT_EINVAL, "jobs is NULL");
+        return BPT_EINVAL;
+    }
+    if (counters) memset(counters, 0, sizeof(*counters));
+    bpt_graph* owner = nullptr;
+    std::vector<uint32_t> live, colors(n_jobs, 0);
+    int nw = 1;
+    try {
+        for (uint32_t i = 0; i < n_jobs; ++i) {
+            bpt_job& jb = jobs[i];
+            jb.total = 0;
+            jb.status = BPT_EINVAL;
+            bpt_graph* gg = check_graph(jb.graph);
+            if (!gg) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) + ": not a bpt_graph handle");
+                return BPT_EINVAL;
+            }
+            if (owner && gg->device != owner->device) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) + ": graphs of one call must share a device");
+                return BPT_EINVAL;
+            }
+            if (!jb.d_offsets || (!jb.d_vertices && jb.capacity > 0) || jb.reserved || jb.reserved2) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) +
+                                           ": d_offsets required (d_vertices when capacity > 0), reserved = 0");
+                return BPT_EINVAL;
+            }
+            if (jb.n_samples >= kMaxSamples || jb.first_sample >= kMaxSamples ||
+                jb.first_sample + jb.n_samples > kMaxSamples) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) + ": sample ids must stay below 2^34");
+                return BPT_EINVAL;
+            }
+            uint32_t c = jb.colors_per_batch ? jb.colors_per_batch : choose_colors(gg, jb.n_samples);
+            if (!valid_colors(c)) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) +
+                                           ": colors_per_batch must be 0 or a power of two from 8 to 1024");
+                return BPT_EINVAL;
+            }
+            colors[i] = c;
+            if (!owner || gg->n > owner->n) owner = gg;
+            if (jb.n_samples > 0) {
+                live.push_back(i);
+                nw = std::max(nw, mask_words(c));
+            }
+        }
+        if (n_jobs == 0) {
+            set_ok();
+            return BPT_OK;
+        }
+        HIP_TRY(hipSetDevice(owner->device));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (uint32_t i = 0; i < n_jobs; ++i) {
+            if (jobs[i].n_samples == 0) {
+                HIP_TRY(hipMemsetAsync(jobs[i].d_offsets, 0, sizeof(uint64_t), st));
+                jobs[i].status = BPT_OK;
+            }
+        }
+        if (live.empty()) {
+            HIP_TRY(hipStreamSynchronize(st));
+            set_ok();
+            return BPT_OK;
+        }
+    } catch (const HipFail& f) {
+        set_status(f.status, f.msg);
+        return f.status;
+    } catch (const std::bad_alloc&) {
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return BPT_ENOMEM;
+    }
+    // one launch per mask width (1, 2, 4, 8, 16 words), widest first
+    (void)nw;
+    Workspace* ws = nullptr;
+    bpt_graph* wowner = nullptr;
+    try {
+        int rc_all = BPT_OK;
+        for (int w = 16; w >= 1; w >>= 1) {
+            std::vector<uint32_t> group;
+            wowner = nullptr;
+            for (uint32_t i : live) {
+                if (mask_words(colors[i]) != w) continue;
+                group.push_back(i);
+                bpt_graph* gg = check_graph(jobs[i].graph);
+                if (!wowner || gg->n > wowner->n) wowner = gg;
+            }
+            if (group.empty()) continue;
+            bpt_counters part{};
+            uint64_t group_batches = 0;
+            for (uint32_t i : group) group_batches += (jobs[i].n_samples + colors[i] - 1) / colors[i];
+            ws = acquire(wowner, w, group_batches);
+            const int rc = run_jobs(wowner, ws, jobs, group, colors, static_cast<hipStream_t>(stream),
+                                    counters ? &part : nullptr);
+            if (rc == BPT_EINTERNAL) delete ws;
+            else release(wowner, ws);
+            ws = nullptr;
+            if (rc != BPT_OK && rc != BPT_ERANGE) return rc;
+            if (rc == BPT_ERANGE) rc_all = BPT_ERANGE;
+            if (counters) {
+                bpt_counters& k = *counters;
+                k.samples += part.samples;
+                k.members += part.members;
+                k.sample_edges += part.sample_edges;
+                k.edge_accesses += part.edge_accesses;
+                k.frontier_entries += part.frontier_entries;
+                k.philox_blocks += part.philox_blocks;
+                k.live_coins += part.live_coins;
+                k.levels += part.levels;
+                k.max_levels = std::max(k.max_levels, part.max_levels);
+                k.batches += part.batches;
+                k.traversal_ns += part.traversal_ns;
+                k.finalize_ns += part.finalize_ns;
+                k.workgroup_size = std::max(k.workgroup_size, part.workgroup_size);
+                k.workgroups = std::max(k.workgroups, part.workgroups);
+            }
+        }
+        if (rc_all == BPT_OK) set_ok();
+        else set_status(BPT_ERANGE, "a job's output capacity is below its total (see the job's total)");
+        return rc_all;
+    } catch (const HipFail& f) {
+        if (ws) release(wowner, ws);
+        set_status(f.status, f.msg);
+        return f.status;
+    } catch (const std::bad_alloc&) {
+        if (ws) release(wowner, ws);
         set_status(BPT_ENOMEM, "host allocation failed");
         return BPT_ENOMEM;
     }
@@ -696,7 +988,7 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
         r->offsets[0] = 0;
         if (n_samples > 0) {
             HIP_TRY(hipSetDevice(gg->device));
-            ws = acquire(gg, mask_words(colors));
+            ws = acquire(gg, mask_words(colors), (n_samples + colors - 1) / colors);
             CallResult res;
             const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, false, nullptr, nullptr, nullptr, 0,
                                         true, &res);
@@ -828,7 +1120,7 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
     try {
         HIP_TRY(hipSetDevice(gg->device));
         for (uint32_t c = 8; c <= 256; c <<= 1) {
-            ws = acquire(gg, mask_words(c));
+            ws = acquire(gg, mask_words(c), (S + c - 1) / c);
             uint64_t ns = ~0ull;
             for (int rep = 0; rep < 2; ++rep) {  // the first run also loads the kernel
                 CallResult res;
@@ -859,6 +1151,7 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
         std::lock_guard<std::mutex> lk(gg->mu);
         gg->tuned[size_bucket(n_samples)] = best;
     }
+    trim_idle(gg, mask_words(best));  // the trial workspaces of the other widths are not kept
     set_ok();
     return best;
 }

@@ -57,9 +57,9 @@ __global__ __launch_bounds__(kScanBlock) void tile_sums(const uint32_t* counts, 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// One workgroup: exclusive scan of the tile sums, total into ctl and offsets[n].
+// One workgroup: exclusive scan of the tile sums, total into *total and offsets[n].
 __global__ __launch_bounds__(kScanBlock) void scan_tiles(unsigned long long* part, uint64_t ntiles, uint64_t n,
-                                                         unsigned long long* offsets, Control* ctl) {
+                                                         unsigned long long* offsets, unsigned long long* total) {
     __shared__ unsigned long long tmp[kScanBlock / kWave];
     unsigned long long carry = 0;
     for (uint64_t b = 0; b < ntiles; b += kScanBlock) {
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_tiles(unsigned long long* par
     }
     if (threadIdx.x == 0) {
         offsets[n] = carry;
-        ctl->total = carry;
+        *total = carry;
     }
 }
 
@@ -102,8 +102,9 @@ __global__ __launch_bounds__(kScanBlock) void tile_offsets(const uint32_t* count
 __global__ __launch_bounds__(256) void gather_sets(const uint32_t* counts, const unsigned long long* where,
                                                    const uint32_t* pool, uint64_t n,
                                                    const unsigned long long* offsets, uint32_t* vertices,
-                                                   unsigned long long capacity, const Control* ctl) {
-    if (ctl->total > capacity || (ctl->err & kErrPoolOverflow)) return;
+                                                   unsigned long long capacity, const unsigned long long* total,
+                                                   const unsigned int* err) {
+    if (*total > capacity || (*err & kErrPoolOverflow)) return;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
@@ -124,22 +125,22 @@ size_t finalize_scratch_bytes(uint64_t n_samples) {
 
 hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
                            uint64_t n_samples, unsigned long long* offsets, uint32_t* vertices,
-                           unsigned long long capacity, Control* ctl, void* scratch, size_t scratch_bytes,
-                           hipStream_t stream) {
+                           unsigned long long capacity, unsigned long long* total, const unsigned int* err,
+                           void* scratch, size_t scratch_bytes, hipStream_t stream) {
     const uint64_t ntiles = (n_samples + kTile - 1) / kTile;
     if (scratch_bytes < finalize_scratch_bytes(n_samples)) return hipErrorInvalidValue;
     unsigned long long* part = static_cast<unsigned long long*>(scratch);
     if (ntiles > 0) {
         hipLaunchKernelGGL(tile_sums, dim3((unsigned)ntiles), dim3(kScanBlock), 0, stream, counts, n_samples, part);
     }
-    hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanBlock), 0, stream, part, ntiles, n_samples, offsets, ctl);
+    hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanBlock), 0, stream, part, ntiles, n_samples, offsets, total);
     if (ntiles > 0) {
         hipLaunchKernelGGL(tile_offsets, dim3((unsigned)ntiles), dim3(kScanBlock), 0, stream, counts, n_samples,
                            part, offsets);
         const uint64_t waves_wanted = n_samples;
         const unsigned blocks = (unsigned)(waves_wanted < 262144 ? (waves_wanted + 3) / 4 : 65536);
         hipLaunchKernelGGL(gather_sets, dim3(blocks), dim3(256), 0, stream, counts, where, pool, n_samples, offsets,
-                           vertices, capacity, ctl);
+                           vertices, capacity, total, err);
     }
     return hipGetLastError();
 }

@@ -75,6 +75,7 @@ struct FusedShared {
     uint32_t qlen[3];  // frontier sizes of levels L, L+1 (and L+2, reset), indexed by level % 3
     uint32_t tlen;
     unsigned long long batch;
+    uint32_t job;
     uint32_t scan_tmp[2][BS / kWave];
     unsigned long long base;
     unsigned long long stats[kNumStats];
@@ -185,9 +186,11 @@ struct BatchCtx {
     unsigned int* err;
 };
 
+// Slot arrays are strided by the largest n of the launch's graphs; b.n is set
+// per batch to the batch's own graph.
 template <int NW>
 __device__ __forceinline__ BatchCtx<NW> slot_ctx(const FusedArgs& a, uint32_t slot) {
-    const uint32_t n = a.g.n;
+    const uint32_t n = a.n_max;
     BatchCtx<NW> b;
     b.n = n;
     b.err = &a.ctl->err;
@@ -268,24 +271,25 @@ __device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
 //    gathered into one mask, so visited[u] and the next frontier take one
 //    atomic per (edge, word) whatever the number of colours (Listing 1).
 template <int NW, int BS>
-__device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
+__device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, uint32_t gather_mode,
+                                            const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
                                             const unsigned long long (&mask)[NW], unsigned long long s0,
                                             uint32_t beg, uint32_t end, uint32_t thr_row, uint32_t q_first,
                                             uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
                                             uint32_t base_tag, unsigned long long& n_philox,
                                             unsigned long long& n_live) {
     static_assert(kQuadsPerItem == 4, "an item's coin words must fit 16 bits");
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t nq = q_end - q_first;
     const uint32_t e_first = q_first << 2;
     // coin words of the item that belong to the row
     uint32_t valid = (end - e_first >= 16u) ? 0xFFFFu : ((1u << (end - e_first)) - 1u);
     if (e_first < beg) valid &= 0xFFFFu << (beg - e_first);
-    const bool per_edge = a.g.prob_layout == BPT_PROB_EDGE;
+    const bool per_edge = g.prob_layout == BPT_PROB_EDGE;
     const uint4 t_row = make_uint4(thr_row, thr_row, thr_row, thr_row);
     // thresholds of quad j of the item (per-edge layout: re-read per colour, an L1 hit)
     auto thr_of = [&](uint32_t j) -> uint4 {
-        return (per_edge && j < nq) ? *reinterpret_cast<const uint4*>(a.g.thr_edge + e_first + 4 * j) : t_row;
+        return (per_edge && j < nq) ? *reinterpret_cast<const uint4*>(g.thr_edge + e_first + 4 * j) : t_row;
     };
     // Gathering pays when an edge is expected to be live for several colours at
     // once: colours of the entry x probability >= 1/2 (per-edge thresholds
@@ -295,8 +299,8 @@ __device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<N
     for (int k = 0; k < NW; ++k) pc += (uint32_t)__popcll(mask[k]);
     const uint32_t p_est = per_edge ? 0x80000000u : thr_row;
     const bool want = pc >= 2 && (unsigned long long)pc * p_est >= 0x80000000ull;
-    const bool gather = a.gather_mode == kGatherAlways ||
-                        (a.gather_mode == kGatherAuto &&
+    const bool gather = gather_mode == kGatherAlways ||
+                        (gather_mode == kGatherAuto &&
                          4 * __popcll(__ballot(want)) >= (unsigned)__popcll(__ballot(true)));
 
     if (gather) {
@@ -328,10 +332,10 @@ __device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<N
                     acc3 |= ((l0 & 8u) ? m0 : 0ull) | ((l1 & 8u) ? m1 : 0ull);
                 }
                 const uint32_t e0 = quad << 2;
-                if (acc0) { n_live += __popcll(acc0); discover_word<NW, BS>(b, s, a.g.col[e0], k, acc0, nxt, qslot, tag, base_tag); }
-                if (acc1) { n_live += __popcll(acc1); discover_word<NW, BS>(b, s, a.g.col[e0 + 1], k, acc1, nxt, qslot, tag, base_tag); }
-                if (acc2) { n_live += __popcll(acc2); discover_word<NW, BS>(b, s, a.g.col[e0 + 2], k, acc2, nxt, qslot, tag, base_tag); }
-                if (acc3) { n_live += __popcll(acc3); discover_word<NW, BS>(b, s, a.g.col[e0 + 3], k, acc3, nxt, qslot, tag, base_tag); }
+                if (acc0) { n_live += __popcll(acc0); discover_word<NW, BS>(b, s, g.col[e0], k, acc0, nxt, qslot, tag, base_tag); }
+                if (acc1) { n_live += __popcll(acc1); discover_word<NW, BS>(b, s, g.col[e0 + 1], k, acc1, nxt, qslot, tag, base_tag); }
+                if (acc2) { n_live += __popcll(acc2); discover_word<NW, BS>(b, s, g.col[e0 + 2], k, acc2, nxt, qslot, tag, base_tag); }
+                if (acc3) { n_live += __popcll(acc3); discover_word<NW, BS>(b, s, g.col[e0 + 3], k, acc3, nxt, qslot, tag, base_tag); }
             }
         }
         return;
@@ -369,7 +373,7 @@ __device__ __forceinline__ void expand_item(const FusedArgs& a, const BatchCtx<N
                 const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
                 live &= live - 1;
                 ++n_live;
-                discover<NW, BS>(b, s, a.g.col[e_first + j], c, nxt, qslot, tag, base_tag);
+                discover<NW, BS>(b, s, g.col[e_first + j], c, nxt, qslot, tag, base_tag);
             }
         }
     }
@@ -462,17 +466,24 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
     }
 }
 
+// Values every lane of the wavefront holds alike, moved to scalar registers.
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+    return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
 template <int NW, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fused_bpt_kernel(FusedArgs a) {
     __shared__ FusedShared<NW, BS> s;
     constexpr uint32_t kSortCap = sort_cap(BS);
     const uint32_t tid = threadIdx.x;
-    const uint32_t n = a.g.n;
     const uint32_t slot = blockIdx.x;
     constexpr uint32_t C = 64u * NW;
-    const BatchCtx<NW> b = slot_ctx<NW>(a, slot);
-    const uint32_t layout = a.g.prob_layout;
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    BatchCtx<NW> b = slot_ctx<NW>(a, slot);
 
     if (tid < kNumStats) s.stats[tid] = 0;
     unsigned long long th_philox = 0, th_live = 0;
@@ -480,20 +491,52 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            s.batch = atomicAdd(&a.ctl->work_counter, 1ull);
+            const unsigned long long bt = atomicAdd(&a.ctl->work_counter, 1ull);
+            uint32_t j = 0;
+            if (a.jobs && bt < a.n_batches) {  // the last job whose first batch is <= bt
+                uint32_t lo = 0, hi = a.n_jobs;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (a.jobs[mid].batch_begin <= bt) lo = mid;
+                    else hi = mid;
+                }
+                j = lo;
+            }
+            s.batch = bt;
+            s.job = j;
         }
         __syncthreads();
-        const uint64_t batch = s.batch;
-        if (batch >= a.n_batches) break;
-        // samples s0 .. s0 + ncol - 1 take colours 0 .. ncol - 1 (a.colors <= C per batch)
-        const uint64_t s0 = a.first_sample + batch * a.colors;
-        const uint32_t ncol = (uint32_t)min((uint64_t)a.colors, a.n_samples - batch * a.colors);
+        if (s.batch >= a.n_batches) break;
+        // the batch's job, in scalar registers
+        const FusedJob* jp = a.jobs ? a.jobs + uni32(s.job) : nullptr;
+        DevGraph g;
+        g.rowptr = uni_ptr(jp ? jp->g.rowptr : a.job0.g.rowptr);
+        g.col = uni_ptr(jp ? jp->g.col : a.job0.g.col);
+        g.thr_row = uni_ptr(jp ? jp->g.thr_row : a.job0.g.thr_row);
+        g.thr_edge = uni_ptr(jp ? jp->g.thr_edge : a.job0.g.thr_edge);
+        g.thr_uniform = uni32(jp ? jp->g.thr_uniform : a.job0.g.thr_uniform);
+        g.prob_layout = uni32(jp ? jp->g.prob_layout : a.job0.g.prob_layout);
+        g.n = uni32(jp ? jp->g.n : a.job0.g.n);
+        g.m = uni32(jp ? jp->g.m : a.job0.g.m);
+        const uint64_t seed = uni64(jp ? jp->seed : a.job0.seed);
+        const uint64_t first = uni64(jp ? jp->first_sample : a.job0.first_sample);
+        const uint64_t n_samples = uni64(jp ? jp->n_samples : a.job0.n_samples);
+        const uint64_t out_base = uni64(jp ? jp->out_base : a.job0.out_base);
+        const uint32_t colors = uni32(jp ? jp->colors : a.job0.colors);
+        const uint64_t batch = uni64(s.batch) - uni64(jp ? jp->batch_begin : a.job0.batch_begin);
+        const uint32_t n = g.n;
+        const uint32_t layout = g.prob_layout;
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        b.n = n;
+        // samples s0 .. s0 + ncol - 1 take colours 0 .. ncol - 1 (colors <= C per batch)
+        const uint64_t s0 = first + batch * colors;
+        const uint32_t ncol = (uint32_t)min((uint64_t)colors, n_samples - batch * colors);
 
         uint32_t base_tag = 0;
         if constexpr (NW > 1) {
             base_tag = a.ws.slot_tag[slot] + 1;
-            if (base_tag > 0xFFFFFFFFu - n - 8u) {  // tags would wrap: restart them
-                for (uint32_t v = tid; v < n; v += BS) store_coherent(&b.stamp[v], 0u);
+            if (base_tag > 0xFFFFFFFFu - a.n_max - 8u) {  // tags would wrap: restart them
+                for (uint32_t v = tid; v < a.n_max; v += BS) store_coherent(&b.stamp[v], 0u);
                 wait_own_memory_ops();
                 __syncthreads();
                 base_tag = 1;
@@ -551,10 +594,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
 #pragma unroll
                 for (uint32_t j = 0; j < kEPT; ++j) {
                     const bool ok = j * BS + tid < cnt;
-                    rb[j] = a.g.rowptr[vq[j]];
-                    re[j] = a.g.rowptr[vq[j] + 1];
-                    rt[j] = layout == BPT_PROB_ROW ? a.g.thr_row[vq[j]]
-                                                   : (layout == BPT_PROB_UNIFORM ? a.g.thr_uniform : 0u);
+                    rb[j] = g.rowptr[vq[j]];
+                    re[j] = g.rowptr[vq[j] + 1];
+                    rt[j] = layout == BPT_PROB_ROW ? g.thr_row[vq[j]]
+                                                   : (layout == BPT_PROB_UNIFORM ? g.thr_uniform : 0u);
 #pragma unroll
                     for (int k = 0; k < NW; ++k)
                         mk[j][k] = ok ? atomicExch(&fr_cur[(size_t)vq[j] * NW + k], 0ull) : 0ull;
@@ -620,7 +663,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     unsigned long long mask[NW];
 #pragma unroll
                     for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
-                    expand_item<NW, BS>(a, b, s, mask, s0, beg, end, s.u.st.thr[i], q_first, q_end, nxt, qnext, tag,
+                    expand_item<NW, BS>(g, seed, a.gather_mode, b, s, mask, s0, beg, end, s.u.st.thr[i], q_first, q_end, nxt, qnext, tag,
                                         base_tag, th_philox, th_live);
                 }
                 set_wave_priority(0);
@@ -650,8 +693,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         __syncthreads();
         const bool write_ok = s.base + s.coff[C - 1] + s.cnt[C - 1] <= a.out.pool_cap;
         for (uint32_t c = tid; c < ncol; c += BS) {
-            a.out.counts[s0 - a.first_sample + c] = s.cnt[c];
-            a.out.where[s0 - a.first_sample + c] = s.base + s.coff[c];
+            a.out.counts[out_base + (s0 - first) + c] = s.cnt[c];
+            a.out.where[out_base + (s0 - first) + c] = s.base + s.coff[c];
         }
 
         const uint32_t* list;

@@ -73,17 +73,28 @@ struct Output {
     unsigned long long pool_cap;
 };
 
-struct FusedArgs {
+// One job of a fused launch: a graph and a range of sample ids under a seed.
+struct FusedJob {
     DevGraph g;
-    FusedSlots ws;
-    Output out;
-    Control* ctl;
     uint64_t seed;
     uint64_t first_sample;
     uint64_t n_samples;
-    uint64_t n_batches;
-    uint32_t colors;
-    uint32_t gather_mode;  // kGatherAuto, kGatherNever or kGatherAlways
+    uint64_t batch_begin;  // first launch-wide batch index of the job
+    uint64_t out_base;     // position of the job's first sample in Output::counts / where
+    uint32_t colors;       // samples per batch (at most 64 * NW)
+    uint32_t pad_;
+};
+
+struct FusedArgs {
+    FusedJob job0;          // the job when `jobs` is null (single-job launches)
+    const FusedJob* jobs;   // device array of n_jobs jobs, by ascending batch_begin, or null
+    uint32_t n_jobs;
+    uint32_t n_max;         // slot stride in vertices: the largest n over the jobs
+    FusedSlots ws;
+    Output out;             // counts / where for all jobs' samples; one shared pool
+    Control* ctl;
+    uint64_t n_batches;     // over all jobs
+    uint32_t gather_mode;   // kGatherAuto, kGatherNever or kGatherAlways
 };
 
 // How the fused expansion schedules an entry's colours (see expand_item):
@@ -112,10 +123,13 @@ __host__ __device__ inline size_t bitmap_words(uint32_t n) { return ((size_t)n +
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStream_t stream);
 hipError_t launch_unfused(const UnfusedArgs& a, int grid, hipStream_t stream);
+// CSR assembly of one job's sets: offsets by a scan of `counts`, then a
+// gather from the pool (skipped when the total exceeds `capacity` or the pool
+// overflowed).  The total goes to offsets[n_samples] and *total.
 hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
                            uint64_t n_samples, unsigned long long* offsets, uint32_t* vertices,
-                           unsigned long long capacity, Control* ctl, void* scratch, size_t scratch_bytes,
-                           hipStream_t stream);
+                           unsigned long long capacity, unsigned long long* total, const unsigned int* err,
+                           void* scratch, size_t scratch_bytes, hipStream_t stream);
 size_t finalize_scratch_bytes(uint64_t n_samples);
 
 constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
