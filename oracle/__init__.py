@@ -237,3 +237,41 @@ def fused_frontier_entries(sets: RRRSets, colors: int) -> int:
         d = sets.dist[lo:hi].astype(np.uint64)
         total += len(np.unique((v << np.uint64(32)) | d))
     return total
+
+
+def greedy_max_cover(offsets: np.ndarray, members: np.ndarray, n: int, k: int) -> tuple[np.ndarray, np.ndarray]:
+    """Influence-maximization seed selection over RRR sets (Section 2: with
+    reverse influence sampling, choosing k seeds is a maximum k-coverage over
+    the sets, and the greedy choice gives a 1 - 1/e approximation).
+
+    k greedy steps; each takes the vertex, among those not chosen yet, that
+    lies in the most sets no chosen vertex covers yet (the lowest id on ties,
+    also when that count is 0), then marks its sets covered.  Returns the seeds
+    and, per step, the number of sets newly covered (int64).  Counts are kept
+    exactly: a vertex's count drops by one for every newly covered set that
+    holds it.
+    """
+    offsets = np.asarray(offsets, dtype=np.int64)
+    members = np.asarray(members, dtype=np.int64)
+    S = len(offsets) - 1
+    set_of = np.repeat(np.arange(S, dtype=np.int64), np.diff(offsets))
+    count = np.bincount(members, minlength=n).astype(np.int64)
+    by_vertex = np.argsort(members, kind="stable")   # positions of each vertex's memberships
+    vstart = np.searchsorted(members[by_vertex], np.arange(n + 1))
+    covered = np.zeros(S, dtype=bool)
+    chosen = np.zeros(n, dtype=bool)
+    seeds = np.zeros(k, dtype=np.int64)
+    gains = np.zeros(k, dtype=np.int64)
+    for step in range(k):
+        cand = np.where(chosen, -1, count)
+        v = int(np.argmax(cand))                      # first maximum: the lowest id
+        seeds[step], gains[step] = v, count[v]
+        chosen[v] = True
+        sets_v = set_of[by_vertex[vstart[v]:vstart[v + 1]]]
+        new = sets_v[~covered[sets_v]]
+        covered[new] = True
+        if len(new):
+            lo, hi = offsets[new], offsets[new + 1]
+            idx = np.concatenate([np.arange(a, b) for a, b in zip(lo.tolist(), hi.tolist())])
+            count -= np.bincount(members[idx], minlength=n)
+    return seeds, gains
