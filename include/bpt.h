@@ -242,6 +242,34 @@ int bpt_graph_release_cache(bpt_graph* g);
  * ---------------------------------------------------------------------- */
 int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counters* counters);
 
+/* ------------------------------------------------------------------------
+ * bpt_max_cover - influence-maximization seeds from sampled RRR sets (paper
+ * Section 2: with reverse influence sampling, choosing k seeds is a maximum
+ * k-coverage over the sets; the greedy choice gives a 1 - 1/e approximation).
+ *
+ * k greedy steps on the device; each takes the vertex, among those not chosen
+ * yet, that lies in the most sets not covered yet (exact integer counts; the
+ * lowest vertex id on ties, also when the count is 0), then covers its sets.
+ *
+ *   d_offsets   device, n_sets + 1 non-decreasing entries from 0; set i is
+ *               d_vertices[d_offsets[i] .. d_offsets[i+1]) (the CSR
+ *               bpt_sample_rrr_device writes).
+ *   d_vertices  device, d_offsets[n_sets] entries, each set ascending and
+ *               without repeats, ids < n.  May be NULL when there are none.
+ *   n_sets      < 2^32.   n  vertex count (>= 1).   k  seeds, k <= n.
+ *   stream      hipStream_t (NULL: default); returns after it has finished.
+ *   seeds       host, k entries (out): the seeds in the order chosen.
+ *   gains       host, k entries (out): sets newly covered by each seed, so
+ *               n * (sum of gains) / n_sets estimates the seeds' influence.
+ *
+ * Device scratch of about 5n + n_sets bytes is allocated per call.  Returns
+ * BPT_OK; BPT_EINVAL for bad arguments, offsets that are not a CSR of
+ * d_vertices, or a member >= n (checked on the device before any set is
+ * touched); BPT_ENOMEM; BPT_EDEVICE.
+ * ---------------------------------------------------------------------- */
+int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
+                  void* stream, uint32_t* seeds, uint64_t* gains);
+
 /* Colour count the library uses for colors_per_batch = 0 on this graph for a
  * job of n_samples samples: the one bpt_tune_colors measured for jobs of this
  * size range, if any; otherwise the widest of 64, 32, 16, 8 that gives every

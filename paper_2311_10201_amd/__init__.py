@@ -21,6 +21,7 @@ __all__ = [
     "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED",
     "BptError", "Counters", "Graph", "Job", "RRRResult",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
+    "bpt_max_cover",
     "bpt_graph_info",
     "bpt_graph_release_cache",
     "bpt_default_colors", "bpt_tune_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
@@ -47,7 +48,7 @@ EXPORTED_SYMBOLS = (
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_rrr_num_samples", "bpt_rrr_num_members",
     "bpt_rrr_offsets", "bpt_rrr_vertices", "bpt_last_status", "bpt_last_error", "bpt_sample_rrr_device",
     "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_tune_colors", "bpt_thr32",
-    "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs",
+    "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs", "bpt_max_cover",
 )
 
 
@@ -137,6 +138,7 @@ def load_library():
         "bpt_sample_rrr_device": (i32, [vp, u64, u64, u32, u64, u32, vp, vp, vp, u64,
                                         ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
         "bpt_sample_rrr_jobs": (i32, [ctypes.POINTER(_Job), u32, vp, ctypes.POINTER(_Counters)]),
+        "bpt_max_cover": (i32, [vp, vp, u64, u32, u32, vp, vp, vp]),
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "bpt_graph_release_cache": (i32, [vp]),
         "bpt_default_colors": (u32, [vp, u64]),
@@ -299,6 +301,18 @@ def bpt_sample_rrr_jobs(jobs, stream=None):
         j.total = int(arr[i].total)
         j.status = int(arr[i].status)
     return st, Counters(**{k: int(getattr(cnt, k)) for k, _ in _Counters._fields_})
+
+
+def bpt_max_cover(d_offsets, d_vertices, n_sets: int, n: int, k: int, stream=None):
+    """Greedy k seeds over device-resident sets.  Returns (seeds, gains) as
+    numpy arrays (uint32, uint64)."""
+    lib = load_library()
+    seeds = np.zeros(max(k, 1), dtype=np.uint32)
+    gains = np.zeros(max(k, 1), dtype=np.uint64)
+    if lib.bpt_max_cover(_addr(d_offsets), _addr(d_vertices), n_sets, n, k, _stream(stream),
+                         seeds.ctypes.data, gains.ctypes.data) != BPT_OK:
+        _raise_last()
+    return seeds[:k], gains[:k]
 
 
 def bpt_graph_info(graph: Graph):

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbpt.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["bpt_capi.cpp", "bpt_graph.cpp", "bpt_fused.hip", "bpt_unfused.hip", "bpt_finalize.hip"]
+SOURCES = ["bpt_capi.cpp", "bpt_graph.cpp", "bpt_fused.hip", "bpt_unfused.hip", "bpt_finalize.hip",
+           "bpt_cover.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -962,6 +962,53 @@ int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counte
     }
 }
 
+int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
+                  void* stream, uint32_t* seeds, uint64_t* gains) {
+    if (!d_offsets || !seeds || !gains || n == 0 || k > n || n_sets >= (1ull << 32)) {
+        set_status(BPT_EINVAL, "d_offsets, seeds and gains are required; 1 <= n, k <= n, n_sets < 2^32");
+        return BPT_EINVAL;
+    }
+    if (k == 0) {
+        set_ok();
+        return BPT_OK;
+    }
+    void* scratch = nullptr;
+    try {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        uint64_t total = 0;
+        HIP_TRY(hipMemcpyAsync(&total, d_offsets + n_sets, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (total > 0 && !d_vertices) {
+            set_status(BPT_EINVAL, "d_vertices is required when the sets have members");
+            return BPT_EINVAL;
+        }
+        HIP_TRY(hipMalloc(&scratch, max_cover_scratch_bytes(n_sets, n, k)));
+        uint32_t* seeds_dev = nullptr;
+        unsigned long long* gains_dev = nullptr;
+        unsigned int* bad_dev = nullptr;
+        HIP_TRY(launch_max_cover(d_offsets, d_vertices, n_sets, total, n, k, scratch, &seeds_dev, &gains_dev,
+                                 &bad_dev, st));
+        unsigned int bad = 0;
+        HIP_TRY(hipMemcpyAsync(seeds, seeds_dev, (size_t)k * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(gains, gains_dev, (size_t)k * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&bad, bad_dev, sizeof(bad), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(scratch));
+        scratch = nullptr;
+        if (bad) {
+            set_status(BPT_EINVAL, (bad & kCoverBadOffsets) ? "offsets are not a CSR of the vertex array"
+                                                            : "a set member is >= n");
+            return BPT_EINVAL;
+        }
+    } catch (const HipFail& f) {
+        if (scratch) (void)hipFree(scratch);
+        set_status(f.status, f.msg);
+        return f.status;
+    }
+    set_ok();
+    return BPT_OK;
+}
+
 bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_batch, uint64_t seed) {
     bpt_graph* gg = check_graph(g);
     if (!gg) {

@@ -134,4 +134,12 @@ size_t finalize_scratch_bytes(uint64_t n_samples);
 
 constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
 
+// Greedy maximum coverage (bpt_cover.hip).  Error bits of its device flag.
+constexpr unsigned int kCoverBadOffsets = 1u;  // offsets not non-decreasing or past the member count
+constexpr unsigned int kCoverBadVertex = 2u;   // a member id >= n
+size_t max_cover_scratch_bytes(uint64_t n_sets, uint32_t n, uint32_t k);
+hipError_t launch_max_cover(const uint64_t* offsets, const uint32_t* vertices, uint64_t n_sets, uint64_t total,
+                            uint32_t n, uint32_t k, void* scratch, uint32_t** seeds_dev,
+                            unsigned long long** gains_dev, unsigned int** bad_dev, hipStream_t stream);
+
 }  // namespace bpt
