@@ -270,6 +270,58 @@ int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counte
 int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
                   void* stream, uint32_t* seeds, uint64_t* gains);
 
+/* ------------------------------------------------------------------------
+ * Serving loop.  A server owns one worker thread on the graphs' device.
+ * Requests submitted from any thread are queued; each worker iteration
+ * admits queued requests in arrival order while their estimated memory (the
+ * sets' expected size from a running per-graph mean, plus per-sample arrays)
+ * fits the budget, always at least one, and at most max_jobs_per_launch;
+ * samples all of them with one bpt_sample_rrr_jobs call; runs bpt_max_cover
+ * for the seed requests; and moves them to a completion queue.  Every
+ * request gets the result it would get alone.
+ * ---------------------------------------------------------------------- */
+typedef struct bpt_server bpt_server;
+
+#define BPT_REQ_SAMPLE 0 /* RRR sets into the request's device buffers            */
+#define BPT_REQ_SEEDS 1  /* sets into server memory, then k greedy seeds (host)   */
+
+typedef struct bpt_request {
+    uint64_t tag;             /* caller's, untouched                                 */
+    bpt_graph* graph;         /* in                                                  */
+    uint64_t first_sample;    /* in: sample ids first_sample .. + n_samples - 1      */
+    uint64_t n_samples;       /* in                                                  */
+    uint64_t seed;            /* in: Philox key                                      */
+    uint32_t kind;            /* in: BPT_REQ_SAMPLE or BPT_REQ_SEEDS                 */
+    uint32_t k;               /* in (SEEDS): seeds wanted, 1 <= k <= n               */
+    uint64_t* d_offsets;      /* in (SAMPLE): device, n_samples + 1 entries          */
+    uint32_t* d_vertices;     /* in (SAMPLE): device, `capacity` entries             */
+    uint64_t capacity;        /* in (SAMPLE)                                         */
+    uint32_t* seeds;          /* in (SEEDS): host, k entries, written                */
+    uint64_t* gains;          /* in (SEEDS): host, k entries, written                */
+    uint64_t total;           /* out: members of the request's sets                  */
+    int32_t status;           /* out: 1 while in flight, then BPT_OK or an error
+                                 (BPT_ERANGE: SAMPLE capacity below total)           */
+    uint32_t reserved;
+    double t_submit;          /* out: server clock (bpt_server_now), seconds         */
+    double t_start;           /* out: its launch began                               */
+    double t_done;            /* out: completed                                      */
+} bpt_request;
+
+/* memory_budget: bytes of admitted work per launch (0: 8 GiB);
+ * max_jobs_per_launch: 0 for 256.  NULL on failure. */
+bpt_server* bpt_server_create(uint64_t memory_budget, uint32_t max_jobs_per_launch);
+/* Queues r; r must stay valid until bpt_server_wait returns it.  BPT_EINVAL
+ * for a bad server or request (missing buffers, k = 0, unknown kind). */
+int bpt_server_submit(bpt_server* s, bpt_request* r);
+/* The next completed request, or NULL after timeout_s seconds. */
+bpt_request* bpt_server_wait(bpt_server* s, double timeout_s);
+/* Seconds since the server was created (the clock of t_submit / t_done). */
+double bpt_server_now(bpt_server* s);
+/* Launches made and requests completed so far. */
+int bpt_server_stats(bpt_server* s, uint64_t* launches, uint64_t* served);
+/* Serves what is queued, then stops the worker and frees the server. */
+int bpt_server_destroy(bpt_server* s);
+
 /* Colour count the library uses for colors_per_batch = 0 on this graph for a
  * job of n_samples samples: the one bpt_tune_colors measured for jobs of this
  * size range, if any; otherwise the widest of 64, 32, 16, 8 that gives every

@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "BPT_OK", "BPT_EINVAL", "BPT_ENOMEM", "BPT_EDEVICE", "BPT_ERANGE", "BPT_EINTERNAL",
     "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED",
-    "BptError", "Counters", "Graph", "Job", "RRRResult",
+    "BptError", "Counters", "Graph", "Job", "RRRResult", "Request", "Server", "BPT_REQ_SAMPLE", "BPT_REQ_SEEDS",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
     "bpt_max_cover",
     "bpt_graph_info",
@@ -49,6 +49,8 @@ EXPORTED_SYMBOLS = (
     "bpt_rrr_offsets", "bpt_rrr_vertices", "bpt_last_status", "bpt_last_error", "bpt_sample_rrr_device",
     "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_tune_colors", "bpt_thr32",
     "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs", "bpt_max_cover",
+    "bpt_server_create", "bpt_server_submit", "bpt_server_wait", "bpt_server_now", "bpt_server_stats",
+    "bpt_server_destroy",
 )
 
 
@@ -79,6 +81,80 @@ class Job:
     colors_per_batch: int = 0
     total: int = 0
     status: int = BPT_OK
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("graph", ctypes.c_void_p), ("first_sample", ctypes.c_uint64),
+                ("n_samples", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("kind", ctypes.c_uint32),
+                ("k", ctypes.c_uint32), ("d_offsets", ctypes.c_void_p), ("d_vertices", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint64), ("seeds", ctypes.c_void_p), ("gains", ctypes.c_void_p),
+                ("total", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+BPT_REQ_SAMPLE = 0
+BPT_REQ_SEEDS = 1
+
+
+class Request:
+    """A queued request of a Server; keeps its C struct and output arrays alive."""
+
+    def __init__(self, kind, graph, first_sample, n_samples, seed, k=0, d_offsets=None, d_vertices=None,
+                 capacity=0, tag=0):
+        self.graph = graph
+        self.d_offsets, self.d_vertices = d_offsets, d_vertices
+        self.seeds = np.zeros(max(k, 1), dtype=np.uint32)
+        self.gains = np.zeros(max(k, 1), dtype=np.uint64)
+        self.k = k
+        self.c = _Request(tag, graph.handle, first_sample, n_samples, seed, kind, k, _addr(d_offsets),
+                          _addr(d_vertices), capacity, self.seeds.ctypes.data, self.gains.ctypes.data,
+                          0, 0, 0, 0.0, 0.0, 0.0)
+
+    tag = property(lambda self: int(self.c.tag))
+    kind = property(lambda self: int(self.c.kind))
+    n_samples = property(lambda self: int(self.c.n_samples))
+    status = property(lambda self: int(self.c.status))
+    total = property(lambda self: int(self.c.total))
+    t_submit = property(lambda self: float(self.c.t_submit))
+    t_start = property(lambda self: float(self.c.t_start))
+    t_done = property(lambda self: float(self.c.t_done))
+
+
+class Server:
+    """The library's serving loop (bpt_server_*): submit from any thread,
+    collect completed requests with wait()."""
+
+    def __init__(self, memory_budget: int = 0, max_jobs_per_launch: int = 0):
+        lib = load_library()
+        self.handle = lib.bpt_server_create(memory_budget, max_jobs_per_launch)
+        if not self.handle:
+            raise BptError(BPT_ENOMEM, "bpt_server_create failed")
+        self._live = {}
+
+    def submit(self, req: Request) -> Request:
+        addr = ctypes.addressof(req.c)
+        self._live[addr] = req
+        if load_library().bpt_server_submit(self.handle, ctypes.byref(req.c)) != BPT_OK:
+            del self._live[addr]
+            raise BptError(BPT_EINVAL, "bpt_server_submit rejected the request")
+        return req
+
+    def wait(self, timeout: float = 1.0):
+        p = load_library().bpt_server_wait(self.handle, timeout)
+        return self._live.pop(p, None) if p else None
+
+    def now(self) -> float:
+        return float(load_library().bpt_server_now(self.handle))
+
+    def stats(self):
+        launches, served = ctypes.c_uint64(), ctypes.c_uint64()
+        load_library().bpt_server_stats(self.handle, ctypes.byref(launches), ctypes.byref(served))
+        return int(launches.value), int(served.value)
+
+    def close(self):
+        if self.handle:
+            load_library().bpt_server_destroy(self.handle)
+            self.handle = None
 
 
 @dataclass
@@ -139,6 +215,12 @@ def load_library():
                                         ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
         "bpt_sample_rrr_jobs": (i32, [ctypes.POINTER(_Job), u32, vp, ctypes.POINTER(_Counters)]),
         "bpt_max_cover": (i32, [vp, vp, u64, u32, u32, vp, vp, vp]),
+        "bpt_server_create": (vp, [u64, u32]),
+        "bpt_server_submit": (i32, [vp, ctypes.POINTER(_Request)]),
+        "bpt_server_wait": (vp, [vp, ctypes.c_double]),
+        "bpt_server_now": (ctypes.c_double, [vp]),
+        "bpt_server_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "bpt_server_destroy": (i32, [vp]),
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "bpt_graph_release_cache": (i32, [vp]),
         "bpt_default_colors": (u32, [vp, u64]),
