@@ -38,6 +38,11 @@ WORKLOADS = {
     "rmat-mix32": dict(kind="mix", instances=32, draw_seed=2311, scale_lo=12, scale_hi=21, efs=(8, 16, 32),
                        probs=(0.01, 0.05, 0.1, "wc"), samples_lo=1_000, samples_hi=200_000, out_budget=1 << 27,
                        check_per_instance=16),
+    # serving: 8 resident weighted-cascade R-MAT graphs (scale 16-22, edge factor 16), Poisson arrivals of
+    # requests for 10k-1M samples (log-uniform), a quarter of them for k = 50 influence-maximization seeds
+    "serve8": dict(kind="serve", scales=(16, 17, 18, 19, 20, 20, 21, 22), ef=16, requests=2000, draw_seed=2023,
+                   samples_lo=10_000, samples_hi=1_000_000, seeds_fraction=0.25, k=50, load=0.8,
+                   check_every=100),
     # Erdos-Renyi n = 1,000, m = 10,000, p = 0.1, 64 samples
     "er1000-p0.1": dict(kind="er", n=1000, m=10_000, graph_seed=42, prob=0.1, samples=64, seed=42, colors=(64,),
                         cpu_stride=1),
@@ -323,6 +328,169 @@ def bench_mix(args, w) -> int:
     return 0 if ok else 1
 
 
+def bench_serve(args, w) -> int:
+    """The serving loop against one-request-at-a-time service of the same
+    Poisson request stream.  One-at-a-time service times are measured request
+    by request (alone on the GPU); its latencies are those of a FIFO queue fed
+    with them.  The server run submits every request at its arrival time and
+    takes latencies from the server's completion stamps."""
+    import math
+    import threading
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_10201_amd as bpt
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    graphs = []
+    for i, sc in enumerate(w["scales"]):
+        src, dst = graphgen.rmat_graph(sc, w["ef"], 0.57, 0.19, 0.19, seed=500 + i)
+        n = 1 << sc
+        graphs.append(dict(n=n, g=bpt.bpt_create_graph(n, src, dst, graphgen.wc_prob(n, dst))))
+    log(f"serve: {len(graphs)} graphs built in {time.perf_counter() - t0:.1f}s")
+    rng = np.random.Generator(np.random.PCG64(w["draw_seed"]))
+    N = args.requests or w["requests"]
+    reqs = []
+    for i in range(N):
+        gi = int(rng.integers(len(graphs)))
+        S = int(round(math.exp(rng.uniform(math.log(w["samples_lo"]), math.log(w["samples_hi"])))))
+        kind = bpt.BPT_REQ_SEEDS if rng.random() < w["seeds_fraction"] else bpt.BPT_REQ_SAMPLE
+        reqs.append(dict(gi=gi, S=S, kind=kind, seed=10_000 + i, first=0))
+    # set-size means per graph (for caller buffers of sample requests)
+    for gr in graphs:
+        off = torch.empty(4097, dtype=torch.int64, device="cuda")
+        cap = 1 << 24
+        st, total, _ = bpt.bpt_sample_rrr_device(gr["g"], 0, 4096, 0, 1, 0, stream, off,
+                                                 torch.empty(cap, dtype=torch.int32, device="cuda"), cap)
+        assert st in (bpt.BPT_OK, bpt.BPT_ERANGE)
+        gr["mean"] = max(1.0, total / 4096)
+
+    def buffers(r):
+        cap = int(r["S"] * graphs[r["gi"]]["mean"] * 2.0) + 65536
+        return (torch.empty(r["S"] + 1, dtype=torch.int64, device="cuda"),
+                torch.empty(cap, dtype=torch.int32, device="cuda"), cap)
+
+    def alone(r):
+        """One request by itself: sets into buffers, plus the seeds for a seed request."""
+        off, vert, cap = buffers(r)
+        g = graphs[r["gi"]]
+        st, total, _ = bpt.bpt_sample_rrr_device(g["g"], r["first"], r["S"], 0, r["seed"], 0, stream, off, vert, cap)
+        assert st == bpt.BPT_OK, st
+        seeds = None
+        if r["kind"] == bpt.BPT_REQ_SEEDS:
+            seeds = bpt.bpt_max_cover(off, vert, r["S"], g["n"], w["k"], stream)[0]
+        return off, vert, total, seeds
+
+    # one at a time: service time of each request alone
+    for r in reqs[:4]:
+        alone(r)
+    torch.cuda.synchronize()
+    service = np.zeros(N)
+    for i, r in enumerate(reqs):
+        t = time.perf_counter()
+        alone(r)
+        torch.cuda.synchronize()
+        service[i] = time.perf_counter() - t
+    for i in range(0, N, max(1, N // 20)):
+        log(f"serve: request {i}: graph {reqs[i]['gi']} samples {reqs[i]['S']} kind {reqs[i]['kind']} "
+            f"alone {service[i] * 1e3:.2f} ms")
+    serial_s = float(service.sum())
+    capacity = N / serial_s
+    load = args.load or w["load"]
+    rate = load * capacity
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, N))
+    fin = np.zeros(N)
+    clock = 0.0
+    for i in range(N):  # FIFO single server
+        clock = max(clock, arrivals[i]) + service[i]
+        fin[i] = clock
+    lat_serial = fin - arrivals
+    samples = sum(r["S"] for r in reqs)
+    log(f"serve: one at a time {serial_s:.1f}s of service, capacity {capacity:.1f} req/s; arrivals at {rate:.1f}/s")
+
+    # the server, same arrival times
+    srv = bpt.Server()
+    done = {}
+
+    def submitter():
+        base = srv.now()
+        for i, r in enumerate(reqs):
+            delay = base + arrivals[i] - srv.now()
+            if delay > 0:
+                time.sleep(delay)
+            g = graphs[r["gi"]]["g"]
+            if r["kind"] == bpt.BPT_REQ_SAMPLE:
+                off, vert, cap = buffers(r)
+                q = bpt.Request(r["kind"], g, r["first"], r["S"], r["seed"], d_offsets=off, d_vertices=vert,
+                                capacity=cap, tag=i)
+            else:
+                q = bpt.Request(r["kind"], g, r["first"], r["S"], r["seed"], k=w["k"], tag=i)
+            q.arrival = base + arrivals[i]
+            srv.submit(q)
+
+    th = threading.Thread(target=submitter)
+    t_run = time.perf_counter()
+    th.start()
+    while len(done) < N:
+        q = srv.wait(30.0)
+        if q is None:
+            log("serve: no completion for 30 s")
+            break
+        done[q.tag] = q
+        if q.kind == bpt.BPT_REQ_SAMPLE and q.tag % w["check_every"]:
+            q.d_offsets = q.d_vertices = None  # free the buffers of requests that are not checked
+        if len(done) % 250 == 0:
+            log(f"serve: {len(done)} of {N} completed")
+    th.join()
+    run_s = time.perf_counter() - t_run
+    info = srv.stats()
+    launches, served = info["launches"], info["served"]
+    srv.close()
+    ok = len(done) == N and all(q.status == bpt.BPT_OK for q in done.values())
+    lat_srv = np.array([done[i].t_done - done[i].arrival for i in range(N)]) if ok else np.zeros(1)
+
+    # results identical alone and in the mix (every check_every-th request)
+    same = ok
+    for i in range(0, N, w["check_every"]):
+        if not same:
+            break
+        q, r = done[i], reqs[i]
+        off, vert, total, seeds = alone(r)
+        torch.cuda.synchronize()
+        if r["kind"] == bpt.BPT_REQ_SAMPLE:
+            same = q.total == total and torch.equal(q.d_offsets, off) and torch.equal(q.d_vertices[:total],
+                                                                                    vert[:total])
+        else:
+            same = q.total == total and np.array_equal(q.seeds[:w["k"]], seeds)
+
+    def pct(x, p):
+        return float(np.percentile(x, p)) * 1e3
+
+    result = {
+        "metric": "RRR requests served (sets or k = 50 influence-maximization seeds): samples/s and p50/p99 "
+                  "latency, serving loop vs one request at a time",
+        "value": samples / run_s, "unit": "samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": run_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": args.workload, "graphs": [f"R-MAT {sc} EF {w['ef']} WC" for sc in w["scales"]],
+                   "requests": N, "samples": samples, "seeds_requests": sum(r["kind"] for r in reqs),
+                   "k": w["k"], "arrival_rate_per_s": rate, "load_vs_one_at_a_time": load},
+        "server": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99), "launches": launches,
+                   "requests_per_launch": served / max(1, launches), "wall_s": run_s,
+                   "worker_s": {k: info[k] for k in ("busy_s", "sample_s", "cover_s", "alloc_s")}},
+        "one_at_a_time": {"p50_ms": pct(lat_serial, 50), "p99_ms": pct(lat_serial, 99), "service_s": serial_s,
+                          "capacity_req_per_s": capacity, "samples_per_s_at_capacity": samples / serial_s},
+        "parity": (f"server results == the same requests alone on {len(range(0, N, w['check_every']))} checked "
+                   "requests" if same else "MISMATCH or failed requests"),
+    }
+    print(json.dumps(result), flush=True)
+    return 0 if same else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +503,9 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (known bytes, for counter scaling)")
     ap.add_argument("--only", default="", help="time only this variant (fused64, fused256, unfused, ...)")
+    ap.add_argument("--requests", type=int, default=0, help="serve8: number of requests (default 2000)")
+    ap.add_argument("--load", type=float, default=0.0,
+                    help="serve8: arrival rate as a multiple of one-at-a-time capacity (default 0.8)")
     ap.add_argument("--tune", action="store_true",
                     help="rmat-mix32: choose each instance's colours with bpt_tune_colors (untimed)")
     ap.add_argument("--fusion-study", default="", metavar="OUT.json",
@@ -359,6 +530,8 @@ def main() -> int:
     w = WORKLOADS[args.workload]
     if w["kind"] == "mix":
         return bench_mix(args, w)
+    if w["kind"] == "serve":
+        return bench_serve(args, w)
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")

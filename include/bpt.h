@@ -317,8 +317,16 @@ int bpt_server_submit(bpt_server* s, bpt_request* r);
 bpt_request* bpt_server_wait(bpt_server* s, double timeout_s);
 /* Seconds since the server was created (the clock of t_submit / t_done). */
 double bpt_server_now(bpt_server* s);
-/* Launches made and requests completed so far. */
-int bpt_server_stats(bpt_server* s, uint64_t* launches, uint64_t* served);
+/* What the worker has done so far. */
+typedef struct bpt_server_info {
+    uint64_t launches; /* bpt_sample_rrr_jobs calls                          */
+    uint64_t served;   /* requests completed                                 */
+    double busy_s;     /* worker time serving groups, seconds                */
+    double sample_s;   /* ... of which in the sampling calls                 */
+    double cover_s;    /* ... in seed selection (incl. its output's release) */
+    double alloc_s;    /* ... allocating seed requests' set buffers          */
+} bpt_server_info;
+int bpt_server_stats(bpt_server* s, bpt_server_info* out);
 /* Serves what is queued, then stops the worker and frees the server. */
 int bpt_server_destroy(bpt_server* s);
 

@@ -92,6 +92,11 @@ class _Request(ctypes.Structure):
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("served", ctypes.c_uint64), ("busy_s", ctypes.c_double),
+                ("sample_s", ctypes.c_double), ("cover_s", ctypes.c_double), ("alloc_s", ctypes.c_double)]
+
+
 BPT_REQ_SAMPLE = 0
 BPT_REQ_SEEDS = 1
 
@@ -146,10 +151,10 @@ class Server:
     def now(self) -> float:
         return float(load_library().bpt_server_now(self.handle))
 
-    def stats(self):
-        launches, served = ctypes.c_uint64(), ctypes.c_uint64()
-        load_library().bpt_server_stats(self.handle, ctypes.byref(launches), ctypes.byref(served))
-        return int(launches.value), int(served.value)
+    def stats(self) -> dict:
+        info = _ServerInfo()
+        load_library().bpt_server_stats(self.handle, ctypes.byref(info))
+        return {name: getattr(info, name) for name, _ in _ServerInfo._fields_}
 
     def close(self):
         if self.handle:
@@ -219,7 +224,7 @@ def load_library():
         "bpt_server_submit": (i32, [vp, ctypes.POINTER(_Request)]),
         "bpt_server_wait": (vp, [vp, ctypes.c_double]),
         "bpt_server_now": (ctypes.c_double, [vp]),
-        "bpt_server_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "bpt_server_stats": (i32, [vp, ctypes.POINTER(_ServerInfo)]),
         "bpt_server_destroy": (i32, [vp]),
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "bpt_graph_release_cache": (i32, [vp]),

@@ -1,5 +1,6 @@
 // C ABI of libbpt: handles, error state, workspaces and the sampling driver.
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -135,6 +136,7 @@ struct bpt_graph {
     std::mutex mu;
     std::vector<bpt::Workspace*> idle;
     uint32_t tuned[64] = {};  // colours measured fastest for jobs of 2^i .. 2^(i+1)-1 samples (0: none)
+    double mean_members = 0;  // running mean set size of this graph's calls (0: none yet), sizes pools
 };
 
 struct bpt_rrr {
@@ -226,6 +228,12 @@ size_t memory_budget() {
 }
 
 // Allocates and zeroes the traversal state of a new workspace.
+// Diagnostics on stderr when BPT_TRACE is set: workspace and pool growth.
+bool trace_on() {
+    static const bool on = getenv("BPT_TRACE") != nullptr;
+    return on;
+}
+
 // Traversal slots a job of `units` batches (fused) or samples (unfused) can
 // keep busy at once, rounded up to a power of two so that workspaces are
 // reused across jobs of similar size.
@@ -289,6 +297,8 @@ Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
             ws->us.slots = ws->slots;
         }
         for (hipEvent_t& e : ws->ev) HIP_TRY(hipEventCreate(&e));
+        if (trace_on())
+            fprintf(stderr, "[libbpt] workspace n=%u nw=%d slots=%u full=%d\n", g->n, nw, ws->slots, (int)ws->full);
         ws->ctl = dev_alloc<Control>(1);
         HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ws->ctl_host), sizeof(Control), hipHostMallocDefault));
         HIP_TRY(hipDeviceSynchronize());
@@ -370,6 +380,8 @@ void ensure_sample_arrays(Workspace* ws, uint64_t n_samples) {
 
 void ensure_pool(bpt_graph* g, Workspace* ws, uint64_t entries) {
     if (ws->pool_cap >= entries) return;
+    if (trace_on()) fprintf(stderr, "[libbpt] pool n=%u %llu -> %llu entries\n", g->n,
+                            (unsigned long long)ws->pool_cap, (unsigned long long)entries);
     dev_free(ws->pool);
     dev_free(ws->out_vertices);
     ws->pool = nullptr;
@@ -384,6 +396,27 @@ void ensure_pool(bpt_graph* g, Workspace* ws, uint64_t entries) {
         ws->pool = dev_alloc<uint32_t>(entries);
     }
     ws->pool_cap = entries;
+}
+
+// Pool entries expected for n_samples sets of graph g: its running mean set
+// size with a margin, so that a launch rarely has to run again after an
+// overflow; without history, 32 per set.
+uint64_t pool_estimate(bpt_graph* g, uint64_t n_samples) {
+    double mean;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        mean = g->mean_members;
+    }
+    const double per = mean > 0 ? mean * 1.3 : 32.0;
+    const double est = std::min<double>((double)n_samples * per, (double)g->n * (double)n_samples);
+    return (uint64_t)est + 1024;
+}
+
+void note_members(bpt_graph* g, uint64_t n_samples, uint64_t total) {
+    if (!n_samples) return;
+    const double m = (double)total / (double)n_samples;
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->mean_members = g->mean_members > 0 ? 0.5 * g->mean_members + 0.5 * m : m;
 }
 
 void ensure_out(Workspace* ws, uint64_t n_samples, uint64_t entries) {
@@ -471,10 +504,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
     }
     ws->have_last = false;
     ensure_sample_arrays(ws, S);
-    if (ws->pool_cap == 0) {
-        const uint64_t guess = std::max<uint64_t>(1u << 20, S * 32);
-        ensure_pool(g, ws, std::min<uint64_t>(guess, (uint64_t)g->n * S));
-    }
+    ensure_pool(g, ws, std::max<uint64_t>(ws->pool_cap ? 0 : (1u << 20), pool_estimate(g, S)));
     for (int attempt = 0; attempt < 8; ++attempt) {
         if (own_output) {
             ensure_out(ws, S, ws->pool_cap);
@@ -542,6 +572,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             return BPT_EINTERNAL;
         }
         res->total = c.total;
+        note_members(g, S, c.total);
         bpt_counters& k = res->counters;
         k.samples = S;
         k.members = c.stats[kStatMembers];
@@ -609,7 +640,11 @@ int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<u
         total_samples += jb.n_samples;
     }
     ensure_sample_arrays(ws, total_samples);
-    if (ws->pool_cap == 0) ensure_pool(owner, ws, std::max<uint64_t>(1u << 20, total_samples * 32));
+    {
+        uint64_t est = 0;
+        for (uint32_t i = 0; i < J; ++i) est += pool_estimate(jobs[live[i]].graph, jobs[live[i]].n_samples);
+        ensure_pool(owner, ws, std::max<uint64_t>(ws->pool_cap ? 0 : (1u << 20), est));
+    }
     for (int attempt = 0; attempt < 8; ++attempt) {
         HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), stream));
         HIP_TRY(hipMemcpyAsync(ws->d_jobs, ws->h_jobs, J * sizeof(FusedJob), hipMemcpyHostToDevice, stream));
@@ -655,6 +690,7 @@ int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<u
         for (uint32_t i = 0; i < J; ++i) {
             bpt_job& jb = jobs[live[i]];
             jb.total = ws->h_totals[i];
+            note_members(jb.graph, jb.n_samples, jb.total);
             jb.status = jb.total > jb.capacity ? BPT_ERANGE : BPT_OK;
             if (jb.status != BPT_OK) rc = BPT_ERANGE;
         }

@@ -48,6 +48,7 @@ struct bpt_server {
     std::deque<bpt_request*> done;
     std::map<const bpt_graph*, double> mean_size;  // members per sample, running estimate per graph
     uint64_t launches = 0, served = 0;
+    double t_sample = 0, t_cover = 0, t_alloc = 0, t_busy = 0;  // worker time, seconds
     bool stop = false;
     std::thread worker;
 
@@ -100,8 +101,15 @@ void finish(bpt_server* sv, bpt_request* r, int status) {
     sv->cv_done.notify_all();
 }
 
+void add_time(bpt_server* sv, double& slot, double since) {
+    const double d = sv->now() - since;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    slot += d;
+}
+
 void serve_group(bpt_server* sv, std::vector<bpt_request*>& group, hipStream_t stream) {
     const size_t G = group.size();
+    const double t_enter = sv->now();
     std::vector<Owned> owned(G);
     std::vector<bpt_job> jobs(G);
     std::vector<size_t> in_launch;  // requests whose job is in the call
@@ -124,7 +132,10 @@ void serve_group(bpt_server* sv, std::vector<bpt_request*>& group, hipStream_t s
                 if (it != sv->mean_size.end()) mean = it->second;
             }
             const uint64_t cap = (uint64_t)((double)r->n_samples * mean * 1.25) + 4096;
-            if (!alloc_owned(owned[i], r->n_samples, cap)) continue;  // left out; fails below
+            const double ta = sv->now();
+            const bool ok = alloc_owned(owned[i], r->n_samples, cap);
+            add_time(sv, sv->t_alloc, ta);
+            if (!ok) continue;  // left out; fails below
             j.d_offsets = owned[i].offsets;
             j.d_vertices = owned[i].vertices;
             j.capacity = owned[i].capacity;
@@ -137,7 +148,9 @@ void serve_group(bpt_server* sv, std::vector<bpt_request*>& group, hipStream_t s
     }
     std::vector<bpt_job> call(in_launch.size());
     for (size_t c = 0; c < in_launch.size(); ++c) call[c] = jobs[in_launch[c]];
+    const double ts = sv->now();
     const int rc = call.empty() ? BPT_OK : bpt_sample_rrr_jobs(call.data(), (uint32_t)call.size(), stream, nullptr);
+    add_time(sv, sv->t_sample, ts);
     for (size_t c = 0; c < in_launch.size(); ++c) jobs[in_launch[c]] = call[c];
     {
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -175,6 +188,7 @@ void serve_group(bpt_server* sv, std::vector<bpt_request*>& group, hipStream_t s
                                            owned[i].offsets, owned[i].vertices, owned[i].capacity, &total, nullptr);
             }
         }
+        const double tc = sv->now();
         if (st == BPT_OK) {
             uint32_t n = 0, layout = 0;
             uint64_t m = 0;
@@ -184,8 +198,10 @@ void serve_group(bpt_server* sv, std::vector<bpt_request*>& group, hipStream_t s
                                    r->gains);
         }
         free_owned(owned[i]);
+        add_time(sv, sv->t_cover, tc);
         finish(sv, r, st);
     }
+    add_time(sv, sv->t_busy, t_enter);
 }
 
 void worker_main(bpt_server* sv) {
@@ -262,12 +278,16 @@ bpt_request* bpt_server_wait(bpt_server* s, double timeout_s) {
     return r;
 }
 
-int bpt_server_stats(bpt_server* s, uint64_t* launches, uint64_t* served) {
+int bpt_server_stats(bpt_server* s, bpt_server_info* out) {
     bpt_server* sv = check_server(s);
-    if (!sv) return BPT_EINVAL;
+    if (!sv || !out) return BPT_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (launches) *launches = sv->launches;
-    if (served) *served = sv->served;
+    out->launches = sv->launches;
+    out->served = sv->served;
+    out->busy_s = sv->t_busy;
+    out->sample_s = sv->t_sample;
+    out->cover_s = sv->t_cover;
+    out->alloc_s = sv->t_alloc;
     return BPT_OK;
 }
 

@@ -53,10 +53,11 @@ def test_server_mixed_requests_match_oracle():
             r = srv.wait(60.0)
             assert r is not None, "server did not complete the requests"
             done.append(r)
-        launches, served = srv.stats()
+        info = srv.stats()
     finally:
         srv.close()
-    assert served == len(reqs) and 1 <= launches <= len(reqs)
+    assert info["served"] == len(reqs) and 1 <= info["launches"] <= len(reqs)
+    assert 0 < info["sample_s"] <= info["busy_s"]
     for r in done:
         gi, kind, first, S, seed, k = specs[r.tag]
         ref = refs[r.tag]
