@@ -202,19 +202,37 @@ class Graph:
         return self.sample_ids(seed, ids, nthreads)
 
 
-def fused_edge_accesses(graph: Graph, sets: RRRSets, colors: int) -> int:
+def _batch_pairs(sets: RRRSets, idx: np.ndarray) -> np.ndarray:
+    """Distinct (vertex, BFS level) pairs reached by the samples ``idx`` of ``sets``."""
+    lo, hi = sets.offsets[idx].astype(np.int64), sets.offsets[idx + 1].astype(np.int64)
+    pos = np.concatenate([np.arange(a, b) for a, b in zip(lo.tolist(), hi.tolist())]) if len(idx) else \
+        np.zeros(0, dtype=np.int64)
+    v = sets.members[pos].astype(np.uint64)
+    d = sets.dist[pos].astype(np.uint64)
+    return np.unique((v << np.uint64(32)) | d)
+
+
+def fused_edge_accesses(graph: Graph, sets: RRRSets, colors: int, order: np.ndarray | None = None) -> int:
     """Edge accesses of a level-synchronous fused traversal (Section 3.2).
 
     Samples are grouped into batches of ``colors`` consecutive entries of
     ``sets`` (which must hold consecutive sample ids starting at a batch
-    boundary).  Within a batch, a vertex v is expanded once per distinct BFS
-    level at which any colour of the batch reaches it, and each expansion
-    examines all indeg(v) incoming edges.  With colors == 1 this equals the
-    total TE of unfused traversals (Theorem 1 holds with equality).
+    boundary), or, when ``order`` is given, of ``order`` (positions in
+    ``sets``; batch b is order[b*colors : (b+1)*colors]).  Within a batch, a
+    vertex v is expanded once per distinct BFS level at which any colour of
+    the batch reaches it, and each expansion examines all indeg(v) incoming
+    edges.  With colors == 1 this equals the total TE of unfused traversals
+    (Theorem 1 holds with equality).
     """
     indeg = graph.indegree()
     total = 0
     count = len(sets)
+    if order is not None:
+        order = np.asarray(order, dtype=np.int64)
+        for b0 in range(0, count, colors):
+            pairs = _batch_pairs(sets, order[b0:b0 + colors])
+            total += int(indeg[(pairs >> np.uint64(32)).astype(np.int64)].sum())
+        return total
     for b0 in range(0, count, colors):
         b1 = min(count, b0 + colors)
         lo, hi = int(sets.offsets[b0]), int(sets.offsets[b1])
@@ -226,8 +244,21 @@ def fused_edge_accesses(graph: Graph, sets: RRRSets, colors: int) -> int:
     return total
 
 
-def fused_frontier_entries(sets: RRRSets, colors: int) -> int:
+def sorted_start_order(sets: RRRSets, rank: np.ndarray | None = None) -> np.ndarray:
+    """Positions of ``sets`` ordered by start vertex (the member at BFS level
+    0), or by ``rank[start]`` when a vertex ranking is given; ties keep
+    sample order (Section 5: batches of traversals with nearby starts)."""
+    starts = sets.members[sets.dist == 0].astype(np.int64)
+    assert len(starts) == len(sets)
+    key = starts if rank is None else np.asarray(rank, dtype=np.int64)[starts]
+    return np.argsort(key, kind="stable")
+
+
+def fused_frontier_entries(sets: RRRSets, colors: int, order: np.ndarray | None = None) -> int:
     """Number of (batch, level, vertex) frontier entries of the same traversal."""
+    if order is not None:
+        order = np.asarray(order, dtype=np.int64)
+        return sum(len(_batch_pairs(sets, order[b0:b0 + colors])) for b0 in range(0, len(sets), colors))
     total = 0
     count = len(sets)
     for b0 in range(0, count, colors):

@@ -320,3 +320,29 @@ def test_empty_graph_and_zero_samples():
     res = g.sample(1, 10)
     assert np.array_equal(np.diff(res.offsets), np.ones(10, dtype=np.uint64))
     assert len(g.sample(1, 0)) == 0
+
+
+def test_ordered_batches_accounting():
+    """The batch-order form of the fused accounting agrees with the id-order
+    form on the identity order, stays within Theorem 1 for any order, and the
+    sorted-start order sorts by the level-0 member."""
+    import graphgen
+    n = 1000
+    src, dst = graphgen.er_graph(n, 10_000, seed=42)
+    og = oracle.Graph(n, src, dst, graphgen.uniform_prob(len(src), 0.1))
+    ref = og.sample(3, 700, nthreads=4)
+    ident = np.arange(len(ref))
+    for c in (1, 8, 64):
+        assert oracle.fused_edge_accesses(og, ref, c, ident) == oracle.fused_edge_accesses(og, ref, c)
+        assert oracle.fused_frontier_entries(ref, c, ident) == oracle.fused_frontier_entries(ref, c)
+    te = int(ref.te.sum())
+    order = oracle.sorted_start_order(ref)
+    starts = np.array([oracle.start_vertex(3, s, n) for s in range(len(ref))])
+    assert np.array_equal(order, np.argsort(starts, kind="stable"))
+    rng = np.random.Generator(np.random.PCG64(1))
+    for o in (order, rng.permutation(len(ref))):
+        assert oracle.fused_edge_accesses(og, ref, 1, o) == te
+        assert oracle.fused_edge_accesses(og, ref, 64, o) <= te
+    rank = rng.permutation(n)
+    o2 = oracle.sorted_start_order(ref, rank)
+    assert np.all(np.diff(rank[starts[o2]]) >= 0)
