@@ -66,6 +66,8 @@ extern "C" {
 
 /* Flags of bpt_sample_rrr_device(). */
 #define BPT_FLAG_UNFUSED 1u /* one traversal per sample (the unfused baseline)  */
+#define BPT_FLAG_SORTED_STARTS 2u /* fused batches of samples with neighbouring start
+                                     vertices (paper Section 5); same sets, same order */
 
 typedef struct bpt_graph bpt_graph; /* opaque, device-resident, immutable */
 typedef struct bpt_rrr bpt_rrr;     /* opaque, host-resident CSR of RRR sets */
@@ -181,7 +183,12 @@ const char* bpt_last_error(void);
  *                     its own range; the sets equal those of one big call).
  *   n_samples         as in bpt_sample_rrr.
  *   colors_per_batch  as in bpt_sample_rrr (ignored with BPT_FLAG_UNFUSED).
- *   flags             0, or BPT_FLAG_UNFUSED for one traversal per sample.
+ *   flags             0; BPT_FLAG_UNFUSED for one traversal per sample; or
+ *                     BPT_FLAG_SORTED_STARTS: the fused batches take the
+ *                     samples in order of their start vertex (ties by id)
+ *                     instead of id order, which can raise colour occupancy;
+ *                     the sets and their order are unchanged (n_samples < 2^31,
+ *                     not with BPT_FLAG_UNFUSED).
  *   stream            hipStream_t to run on (NULL = the default stream).
  *   d_offsets         device array of n_samples+1 uint64: written with the
  *                     CSR offsets (d_offsets[0] = 0).
@@ -329,6 +336,21 @@ typedef struct bpt_server_info {
 int bpt_server_stats(bpt_server* s, bpt_server_info* out);
 /* Serves what is queued, then stops the worker and frees the server. */
 int bpt_server_destroy(bpt_server* s);
+
+/* ------------------------------------------------------------------------
+ * bpt_graph_set_vertex_order - a locality-preserving vertex order for sorted
+ * starts (paper Section 5: reordering, e.g. reverse Cuthill-McKee, then
+ * batching traversals with nearby starts).  With BPT_FLAG_SORTED_STARTS,
+ * samples are batched in order of rank[start] instead of the start's id.
+ * Nothing is relabelled: coins stay keyed on the original vertex and edge
+ * ids, so the sets are unchanged.
+ *
+ *   rank  host array of n entries, a permutation of 0 .. n-1 (copied); NULL
+ *         returns to id order.
+ * Not to be called while a sampling call on the same graph is running.
+ * Returns BPT_OK, BPT_EINVAL (bad handle, not a permutation), BPT_ENOMEM.
+ * ---------------------------------------------------------------------- */
+int bpt_graph_set_vertex_order(bpt_graph* g, const uint32_t* rank);
 
 /* Colour count the library uses for colors_per_batch = 0 on this graph for a
  * job of n_samples samples: the one bpt_tune_colors measured for jobs of this

@@ -18,11 +18,11 @@ import numpy as np
 
 __all__ = [
     "BPT_OK", "BPT_EINVAL", "BPT_ENOMEM", "BPT_EDEVICE", "BPT_ERANGE", "BPT_EINTERNAL",
-    "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED",
+    "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED", "BPT_FLAG_SORTED_STARTS",
     "BptError", "Counters", "Graph", "Job", "RRRResult", "Request", "Server", "BPT_REQ_SAMPLE", "BPT_REQ_SEEDS",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
     "bpt_max_cover",
-    "bpt_graph_info",
+    "bpt_graph_info", "bpt_graph_set_vertex_order",
     "bpt_graph_release_cache",
     "bpt_default_colors", "bpt_tune_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
     "bpt_last_status", "bpt_last_error", "library_path", "load_library",
@@ -38,6 +38,7 @@ BPT_PROB_UNIFORM = 0
 BPT_PROB_ROW = 1
 BPT_PROB_EDGE = 2
 BPT_FLAG_UNFUSED = 1
+BPT_FLAG_SORTED_STARTS = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libbpt.so")
@@ -50,7 +51,7 @@ EXPORTED_SYMBOLS = (
     "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_tune_colors", "bpt_thr32",
     "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs", "bpt_max_cover",
     "bpt_server_create", "bpt_server_submit", "bpt_server_wait", "bpt_server_now", "bpt_server_stats",
-    "bpt_server_destroy",
+    "bpt_server_destroy", "bpt_graph_set_vertex_order",
 )
 
 
@@ -226,6 +227,7 @@ def load_library():
         "bpt_server_now": (ctypes.c_double, [vp]),
         "bpt_server_stats": (i32, [vp, ctypes.POINTER(_ServerInfo)]),
         "bpt_server_destroy": (i32, [vp]),
+        "bpt_graph_set_vertex_order": (i32, [vp, vp]),
         "bpt_graph_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "bpt_graph_release_cache": (i32, [vp]),
         "bpt_default_colors": (u32, [vp, u64]),
@@ -408,6 +410,13 @@ def bpt_graph_info(graph: Graph):
     if lib.bpt_graph_info(graph.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(lay)) != BPT_OK:
         _raise_last()
     return int(n.value), int(m.value), int(lay.value)
+
+
+def bpt_graph_set_vertex_order(graph: Graph, rank) -> None:
+    """Vertex order for sorted starts (a permutation of 0..n-1), or None."""
+    arr = None if rank is None else np.ascontiguousarray(rank, dtype=np.uint32)
+    if load_library().bpt_graph_set_vertex_order(graph.handle, None if arr is None else arr.ctypes.data) != BPT_OK:
+        _raise_last()
 
 
 def bpt_graph_release_cache(graph: Graph) -> None:

@@ -89,6 +89,8 @@ struct Workspace {
     unsigned long long* d_totals = nullptr;
     unsigned long long* h_totals = nullptr;
     uint32_t jobs_cap = 0;
+    void* order_scratch = nullptr;  // sorted starts: keys, indices and sort temporaries
+    size_t order_bytes = 0;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // traversal start, traversal end, finalize end
     // When a call ends in BPT_ERANGE its sets stay in counts / where / pool;
     // the retry with a larger buffer and the same arguments only re-runs the
@@ -96,7 +98,7 @@ struct Workspace {
     bool have_last = false;
     uint64_t last_first = 0, last_samples = 0, last_seed = 0;
     uint32_t last_colors = 0;
-    bool last_unfused = false;
+    uint32_t last_flags = 0;
     bpt_counters last_counters{};
 
     ~Workspace() {
@@ -113,6 +115,7 @@ struct Workspace {
         dev_free(out_vertices);
         dev_free(d_jobs);
         dev_free(d_totals);
+        dev_free(order_scratch);
         if (h_jobs) (void)hipHostFree(h_jobs);
         if (h_totals) (void)hipHostFree(h_totals);
     }
@@ -137,6 +140,7 @@ struct bpt_graph {
     std::vector<bpt::Workspace*> idle;
     uint32_t tuned[64] = {};  // colours measured fastest for jobs of 2^i .. 2^(i+1)-1 samples (0: none)
     double mean_members = 0;  // running mean set size of this graph's calls (0: none yet), sizes pools
+    uint32_t* d_rank = nullptr;  // vertex order for sorted starts (null: vertex ids)
 };
 
 struct bpt_rrr {
@@ -470,10 +474,12 @@ void release_or_discard(bpt_graph* g, Workspace* ws, const CallResult& r) {
 // Runs the traversal and the CSR assembly.  When `own_output` is set the
 // result goes to the workspace's own device buffers (sized to fit).
 int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32_t colors, uint64_t seed,
-                 bool unfused, hipStream_t stream, unsigned long long* d_offsets, uint32_t* d_vertices,
+                 uint32_t flags, hipStream_t stream, unsigned long long* d_offsets, uint32_t* d_vertices,
                  uint64_t capacity, bool own_output, CallResult* res) {
+    const bool unfused = (flags & BPT_FLAG_UNFUSED) != 0;
+    const bool sorted = (flags & BPT_FLAG_SORTED_STARTS) != 0;
     const bool reuse = ws->have_last && ws->last_first == first && ws->last_samples == S &&
-                       ws->last_seed == seed && ws->last_colors == colors && ws->last_unfused == unfused;
+                       ws->last_seed == seed && ws->last_colors == colors && ws->last_flags == flags;
     if (reuse) {
         if (own_output) {
             ensure_out(ws, S, ws->pool_cap);
@@ -521,7 +527,21 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
         out.pool = ws->pool;
         out.pool_cap = ws->pool_cap;
         if (!unfused) {
+            const uint32_t* order = nullptr;
+            if (sorted) {  // batches of samples with neighbouring start vertices
+                const size_t need = order_scratch_bytes(S, g->n);
+                if (ws->order_bytes < need) {
+                    dev_free(ws->order_scratch);
+                    ws->order_scratch = nullptr;
+                    ws->order_bytes = 0;
+                    ws->order_scratch = dev_alloc<char>(need);
+                    ws->order_bytes = need;
+                }
+                HIP_TRY(launch_sort_by_start(g->n, seed, first, S, g->d_rank, ws->order_scratch, ws->order_bytes,
+                                             &order, stream));
+            }
             FusedArgs a = {};
+            a.job0.order = order;
             a.job0.g = dev_graph(g);
             a.job0.seed = seed;
             a.job0.first_sample = first;
@@ -597,7 +617,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             ws->last_samples = S;
             ws->last_seed = seed;
             ws->last_colors = colors;
-            ws->last_unfused = unfused;
+            ws->last_flags = flags;
             ws->last_counters = k;
             set_status(BPT_ERANGE, "output capacity " + std::to_string(capacity) + " < " + std::to_string(c.total) +
                                        " members");
@@ -816,8 +836,9 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
         set_status(BPT_EINVAL, "d_offsets and total_out are required (d_vertices when capacity > 0)");
         return BPT_EINVAL;
     }
-    if (flags & ~BPT_FLAG_UNFUSED) {
-        set_status(BPT_EINVAL, "unknown flag bits");
+    if ((flags & ~(BPT_FLAG_UNFUSED | BPT_FLAG_SORTED_STARTS)) ||
+        ((flags & BPT_FLAG_SORTED_STARTS) && ((flags & BPT_FLAG_UNFUSED) || n_samples >= (1ull << 31)))) {
+        set_status(BPT_EINVAL, "unknown flag bits, or sorted starts with the unfused traversal or >= 2^31 samples");
         return BPT_EINVAL;
     }
     const bool unfused = (flags & BPT_FLAG_UNFUSED) != 0;
@@ -847,7 +868,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
         }
         ws = acquire(gg, unfused ? 0 : mask_words(colors), unfused ? n_samples : (n_samples + colors - 1) / colors);
         CallResult res;
-        const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, unfused, st,
+        const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, flags, st,
                                     reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity, false,
                                     &res);
         release_or_discard(gg, ws, res);
@@ -998,6 +1019,43 @@ int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counte
     }
 }
 
+int bpt_graph_set_vertex_order(bpt_graph* g, const uint32_t* rank) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return BPT_EINVAL;
+    }
+    uint32_t* d = nullptr;
+    if (rank) {
+        std::vector<uint8_t> seen(gg->n, 0);
+        for (uint32_t v = 0; v < gg->n; ++v) {
+            if (rank[v] >= gg->n || seen[rank[v]]) {
+                set_status(BPT_EINVAL, "rank must be a permutation of 0 .. n-1");
+                return BPT_EINVAL;
+            }
+            seen[rank[v]] = 1;
+        }
+        try {
+            HIP_TRY(hipSetDevice(gg->device));
+            d = dev_alloc<uint32_t>(gg->n);
+            HIP_TRY(hipMemcpy(d, rank, (size_t)gg->n * sizeof(uint32_t), hipMemcpyHostToDevice));
+        } catch (const HipFail& f) {
+            dev_free(d);
+            set_status(f.status, f.msg);
+            return f.status;
+        }
+    }
+    uint32_t* old = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(gg->mu);
+        old = gg->d_rank;
+        gg->d_rank = d;
+    }
+    dev_free(old);
+    set_ok();
+    return BPT_OK;
+}
+
 int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
                   void* stream, uint32_t* seeds, uint64_t* gains) {
     if (!d_offsets || !seeds || !gains || n == 0 || k > n || n_sets >= (1ull << 32)) {
@@ -1073,7 +1131,7 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
             HIP_TRY(hipSetDevice(gg->device));
             ws = acquire(gg, mask_words(colors), (n_samples + colors - 1) / colors);
             CallResult res;
-            const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, false, nullptr, nullptr, nullptr, 0,
+            const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, 0u, nullptr, nullptr, nullptr, 0,
                                         true, &res);
             if (rc != BPT_OK) {
                 release_or_discard(gg, ws, res);
@@ -1127,6 +1185,7 @@ void bpt_free(void* handle) {
         dev_free(g->d_col);
         dev_free(g->d_thr_row);
         dev_free(g->d_thr_edge);
+        dev_free(g->d_rank);
         delete g;
         set_ok();
     } else if (magic == kRrrMagic) {
@@ -1207,7 +1266,7 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
             uint64_t ns = ~0ull;
             for (int rep = 0; rep < 2; ++rep) {  // the first run also loads the kernel
                 CallResult res;
-                const int rc = run_sampling(gg, ws, 0, S, c, seed, false, nullptr, nullptr, nullptr, 0, true, &res);
+                const int rc = run_sampling(gg, ws, 0, S, c, seed, 0u, nullptr, nullptr, nullptr, 0, true, &res);
                 if (rc != BPT_OK) {
                     release_or_discard(gg, ws, res);
                     return 0;  // status set by run_sampling

@@ -72,6 +72,7 @@ struct FusedShared {
     } u;
     unsigned long long coff[64 * NW];  // first pool position of each colour's set
     uint32_t cnt[64 * NW];             // members per colour (found by this workgroup)
+    uint32_t cidx[64 * NW];            // sorted starts: sample index (from the job's first) of each colour
     uint32_t qlen[3];  // frontier sizes of levels L, L+1 (and L+2, reset), indexed by level % 3
     uint32_t tlen;
     unsigned long long batch;
@@ -274,6 +275,7 @@ template <int NW, int BS>
 __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, uint32_t gather_mode,
                                             const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
                                             const unsigned long long (&mask)[NW], unsigned long long s0,
+                                            unsigned long long first, bool ordered,
                                             uint32_t beg, uint32_t end, uint32_t thr_row, uint32_t q_first,
                                             uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
                                             uint32_t base_tag, unsigned long long& n_philox,
@@ -319,9 +321,10 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
                     const bool h1 = mk != 0;
                     const uint32_t b1 = h1 ? (uint32_t)(__ffsll((long long)mk) - 1) : b0;
                     mk &= h1 ? mk - 1 : mk;
-                    const unsigned long long sk = s0 + (unsigned long long)k * 64u;
-                    const Block4 r0 = coin_block(quad, sk + b0, k0, k1);
-                    const Block4 r1 = coin_block(quad, sk + b1, k0, k1);
+                    const unsigned long long sa = ordered ? first + s.cidx[k * 64 + b0] : s0 + k * 64u + b0;
+                    const unsigned long long sb = ordered ? first + s.cidx[k * 64 + b1] : s0 + k * 64u + b1;
+                    const Block4 r0 = coin_block(quad, sa, k0, k1);
+                    const Block4 r1 = coin_block(quad, sb, k0, k1);
                     n_philox += h1 ? 2u : 1u;
                     const uint32_t l0 = live_bits(r0, t) & vq;
                     const uint32_t l1 = h1 ? live_bits(r1, t) & vq : 0u;
@@ -350,7 +353,7 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
             const uint32_t bpos = (uint32_t)(__ffsll((long long)mk) - 1);
             mk &= mk - 1;
             const uint32_t c = (uint32_t)k * 64u + bpos;
-            const unsigned long long sc = s0 + c;
+            const unsigned long long sc = ordered ? first + s.cidx[c] : s0 + c;  // colour c's sample
             uint32_t live;
             if (wide) {
                 const Block4 r0 = coin_block(q_first, sc, k0, k1);
@@ -523,6 +526,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         const uint64_t n_samples = uni64(jp ? jp->n_samples : a.job0.n_samples);
         const uint64_t out_base = uni64(jp ? jp->out_base : a.job0.out_base);
         const uint32_t colors = uni32(jp ? jp->colors : a.job0.colors);
+        const uint32_t* order = uni_ptr(jp ? jp->order : a.job0.order);
+        const bool ordered = order != nullptr;
         const uint64_t batch = uni64(s.batch) - uni64(jp ? jp->batch_begin : a.job0.batch_begin);
         const uint32_t n = g.n;
         const uint32_t layout = g.prob_layout;
@@ -543,6 +548,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
             }
         }
         for (uint32_t c = tid; c < C; c += BS) s.cnt[c] = 0;
+        if (ordered)
+            for (uint32_t c = tid; c < ncol; c += BS) s.cidx[c] = order[batch * colors + c];
         if (tid == 0) {
             s.qlen[0] = 0;
             s.qlen[1] = 0;
@@ -553,7 +560,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
 
         // Frontier initialisation: colour c starts at its sample's start vertex.
         for (uint32_t c = tid; c < ncol; c += BS)
-            discover<NW, BS>(b, s, start_of(s0 + c, n, k0, k1), c, 0, 0, base_tag, base_tag);
+            discover<NW, BS>(b, s, start_of(ordered ? first + s.cidx[c] : s0 + c, n, k0, k1), c, 0, 0, base_tag,
+                             base_tag);
 
         // Level-synchronous fused traversal.
         uint32_t level = 0, scan_buf = 0;
@@ -663,8 +671,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     unsigned long long mask[NW];
 #pragma unroll
                     for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
-                    expand_item<NW, BS>(g, seed, a.gather_mode, b, s, mask, s0, beg, end, s.u.st.thr[i], q_first, q_end, nxt, qnext, tag,
-                                        base_tag, th_philox, th_live);
+                    expand_item<NW, BS>(g, seed, a.gather_mode, b, s, mask, s0, first, ordered, beg, end,
+                                        s.u.st.thr[i], q_first, q_end, nxt, qnext, tag, base_tag, th_philox,
+                                        th_live);
                 }
                 set_wave_priority(0);
                 if (c0 + kChunk < F) __syncthreads();  // the next chunk reuses the staging area
@@ -693,8 +702,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         __syncthreads();
         const bool write_ok = s.base + s.coff[C - 1] + s.cnt[C - 1] <= a.out.pool_cap;
         for (uint32_t c = tid; c < ncol; c += BS) {
-            a.out.counts[out_base + (s0 - first) + c] = s.cnt[c];
-            a.out.where[out_base + (s0 - first) + c] = s.base + s.coff[c];
+            const uint64_t si = ordered ? (uint64_t)s.cidx[c] : (s0 - first) + c;  // the sample's output slot
+            a.out.counts[out_base + si] = s.cnt[c];
+            a.out.where[out_base + si] = s.base + s.coff[c];
         }
 
         const uint32_t* list;

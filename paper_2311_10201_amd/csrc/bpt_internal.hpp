@@ -83,6 +83,7 @@ struct FusedJob {
     uint64_t out_base;     // position of the job's first sample in Output::counts / where
     uint32_t colors;       // samples per batch (at most 64 * NW)
     uint32_t pad_;
+    const uint32_t* order; // batch composition: batch b takes samples first + order[b*colors ..] (null: in id order)
 };
 
 struct FusedArgs {
@@ -133,6 +134,12 @@ hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* whe
 size_t finalize_scratch_bytes(uint64_t n_samples);
 
 constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
+
+// Sorted starts (bpt_order.hip): order[i] = indices 0 .. S-1 of samples
+// first .. first+S-1 sorted by start vertex (ties by index).
+size_t order_scratch_bytes(uint64_t n_samples, uint32_t n);
+hipError_t launch_sort_by_start(uint32_t n, uint64_t seed, uint64_t first, uint64_t n_samples, const uint32_t* rank,
+                                void* scratch, size_t scratch_bytes, const uint32_t** order, hipStream_t stream);
 
 // Greedy maximum coverage (bpt_cover.hip).  Error bits of its device flag.
 constexpr unsigned int kCoverBadOffsets = 1u;  // offsets not non-decreasing or past the member count
