@@ -177,6 +177,74 @@ def fusion_study(out_path: str) -> int:
     return 0
 
 
+def order_study(out_path: str) -> int:
+    """Batch composition (the paper's heuristics of Section 5): samples in id
+    order, sorted by start vertex, and sorted by the start's rank in a reverse
+    Cuthill-McKee order of the graph.  Edge accesses, colour occupancy and
+    traversal time of the same sets under each."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+
+    import graphgen
+    import paper_2311_10201_amd as bpt
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cases = []
+    src, dst = graphgen.rmat_graph(20, 16, 0.57, 0.19, 0.19, seed=20)
+    cases.append(("R-MAT 20 WC", 1 << 20, src, dst, graphgen.wc_prob(1 << 20, dst), 100_000, 42))
+    src, dst = graphgen.rmat_graph(22, 16, 0.57, 0.19, 0.19, seed=22)
+    cases.append(("R-MAT 22 p=0.01", 1 << 22, src, dst, graphgen.uniform_prob(len(src), 0.01), 100_000, 42))
+    for deg, p in ((16, 0.1), (16, 0.2), (4, 0.4)):
+        src, dst = graphgen.lfr_graph(10_000, deg, 2)
+        cases.append((f"LFR n=10k degree {deg} p={p}", 10_000, src, dst, graphgen.uniform_prob(len(src), p), 10_240, 1))
+    rows = []
+    for name, n, src, dst, prob, S, seed in cases:
+        a = sp.csr_matrix((np.ones(len(src), dtype=np.float32), (src, dst)), shape=(n, n))
+        t = time.perf_counter()
+        perm = reverse_cuthill_mckee((a + a.T).tocsr(), symmetric_mode=True)
+        rank = np.empty(n, dtype=np.uint32)
+        rank[perm] = np.arange(n, dtype=np.uint32)
+        log(f"order study: {name}: RCM in {time.perf_counter() - t:.1f}s")
+        g = bpt.bpt_create_graph(n, src, dst, prob)
+        off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+        cap = 1 << 22
+        vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+        for C in (64, 256):
+            for label, flags, rk in (("sample ids", 0, None), ("sorted starts", bpt.BPT_FLAG_SORTED_STARTS, None),
+                                     ("sorted RCM ranks", bpt.BPT_FLAG_SORTED_STARTS, rank)):
+                bpt.bpt_graph_set_vertex_order(g, rk)
+                times = []
+                for rep in range(4):
+                    st, total, cnt = bpt.bpt_sample_rrr_device(g, 0, S, C, seed, flags, stream, off, vert, cap)
+                    if st == bpt.BPT_ERANGE:
+                        cap = total + total // 8
+                        vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+                        st, total, cnt = bpt.bpt_sample_rrr_device(g, 0, S, C, seed, flags, stream, off, vert, cap)
+                    assert st == bpt.BPT_OK
+                    if rep:
+                        times.append(cnt.traversal_ns / 1e6)
+                rows.append(dict(case=name, colors=C, order=label, ea=cnt.edge_accesses, te=cnt.sample_edges,
+                                 entries=cnt.frontier_entries, members=cnt.members,
+                                 traversal_ms=float(np.median(times))))
+                log(f"order study: {name} C={C} {label}: EA/TE {cnt.edge_accesses / max(1, cnt.sample_edges):.4f} "
+                    f"{np.median(times):.3f} ms")
+        bpt.bpt_free(g)
+        del vert, off
+        torch.cuda.empty_cache()
+    with open(out_path, "w") as f:
+        json.dump(rows, f)
+    print("| graph | C | batch order | EA / TE | colour occupancy | traversal ms |")
+    print("|---|---|---|---|---|---|")
+    for r in rows:
+        occ = r["members"] / max(1, r["colors"] * r["entries"])
+        print(f"| {r['case']} | {r['colors']} | {r['order']} | {r['ea'] / max(1, r['te']):.4f} | {100 * occ:.2f}% | "
+              f"{r['traversal_ms']:.3f} |")
+    return 0
+
+
 def mix_instances(w):
     """The seeded draw of the mix's instances (shapes only; graphs come later)."""
     import math
@@ -508,6 +576,8 @@ def main() -> int:
                     help="serve8: arrival rate as a multiple of one-at-a-time capacity (default 0.8)")
     ap.add_argument("--tune", action="store_true",
                     help="rmat-mix32: choose each instance's colours with bpt_tune_colors (untimed)")
+    ap.add_argument("--order-study", default="", metavar="OUT.json",
+                    help="instead of the benchmark: id-order vs sorted-start vs RCM-sorted batches")
     ap.add_argument("--fusion-study", default="", metavar="OUT.json",
                     help="instead of the benchmark: edge accesses and colour occupancy of the fused traversal "
                          "vs colour count and probability on LFR graphs; writes the records to OUT.json")
@@ -521,6 +591,8 @@ def main() -> int:
 
     if args.fusion_study:
         return fusion_study(args.fusion_study)
+    if args.order_study:
+        return order_study(args.order_study)
 
     import numpy as np
     import torch
