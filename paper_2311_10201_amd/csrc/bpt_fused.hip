@@ -10,7 +10,7 @@
 //                    the current depth (Listing 1's frontier[v]).
 //   expansion        every in-edge e = (u -> v) of the entry is tried for
 //                    every colour of the mask.  Work items are (entry, up to
-//                    four 4-edge quads) spread evenly over the workgroup's
+//                    eight 4-edge quads) spread evenly over the workgroup's
 //                    lanes; each evaluates one Philox block per colour and
 //                    quad, i.e. the coins of four consecutive in-edges.
 //                    Coins are flipped before any neighbour data is read
@@ -47,7 +47,7 @@ constexpr int ept(int nw, int bs) {
     return nw == 1 ? (bs <= 512 ? 4 : 2) : (nw == 2 ? (bs <= 256 ? 4 : 2) : (nw == 4 && bs <= 256 ? 2 : 1));
 }
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kQuadsPerItem = 4;  // 4-edge quads one work item covers (one entry lookup)
+constexpr uint32_t kQuadsPerItem = 8;  // 4-edge quads one work item covers (one entry lookup)
 
 template <int NW, int BS>
 struct Stage {  // traversal staging of one chunk of ept(NW, BS) * BS frontier entries
@@ -263,10 +263,10 @@ __device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
 // the row [beg, end) for every colour in `mask`, and discovery of the live
 // ones.  Two schedules, chosen per wavefront (FusedArgs::gather_mode):
 //  * mostly one colour per entry: the item's Philox blocks of a colour are
-//    independent and are evaluated side by side (all four when the mask is one
-//    word and any lane has more than two quads, else in pairs), so that a
-//    wavefront alone on its SIMD still keeps the multiplier pipeline busy;
-//    each live coin is discovered on its own;
+//    independent and are evaluated side by side (in rounds of four when the
+//    mask is one word and any lane has more than two quads, else in pairs),
+//    so that a wavefront alone on its SIMD still keeps the multiplier
+//    pipeline busy; each live coin is discovered on its own;
 //  * several colours per entry: per (quad, mask word) the blocks of two
 //    colours are evaluated side by side and each edge's live colours are
 //    gathered into one mask, so visited[u] and the next frontier take one
@@ -280,13 +280,13 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
                                             uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
                                             uint32_t base_tag, unsigned long long& n_philox,
                                             unsigned long long& n_live) {
-    static_assert(kQuadsPerItem == 4, "an item's coin words must fit 16 bits");
+    static_assert(kQuadsPerItem % 4 == 0 && kQuadsPerItem <= 8, "an item's coin words must fit 32 bits");
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t nq = q_end - q_first;
     const uint32_t e_first = q_first << 2;
     // coin words of the item that belong to the row
-    uint32_t valid = (end - e_first >= 16u) ? 0xFFFFu : ((1u << (end - e_first)) - 1u);
-    if (e_first < beg) valid &= 0xFFFFu << (beg - e_first);
+    uint32_t valid = (end - e_first >= 32u) ? 0xFFFFFFFFu : ((1u << (end - e_first)) - 1u);
+    if (e_first < beg) valid &= 0xFFFFFFFFu << (beg - e_first);
     const bool per_edge = g.prob_layout == BPT_PROB_EDGE;
     const uint4 t_row = make_uint4(thr_row, thr_row, thr_row, thr_row);
     // thresholds of quad j of the item (per-edge layout: re-read per colour, an L1 hit)
@@ -356,12 +356,16 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
             const unsigned long long sc = ordered ? first + s.cidx[c] : s0 + c;  // colour c's sample
             uint32_t live;
             if (wide) {
-                const Block4 r0 = coin_block(q_first, sc, k0, k1);
-                const Block4 r1 = coin_block(q_first + 1, sc, k0, k1);
-                const Block4 r2 = coin_block(q_first + 2, sc, k0, k1);
-                const Block4 r3 = coin_block(q_first + 3, sc, k0, k1);
-                live = live_bits(r0, thr_of(0)) | (live_bits(r1, thr_of(1)) << 4) | (live_bits(r2, thr_of(2)) << 8) |
-                       (live_bits(r3, thr_of(3)) << 12);
+                live = 0;
+                for (uint32_t j = 0; j < nq; j += 4) {  // rounds of four quads
+                    const Block4 r0 = coin_block(q_first + j, sc, k0, k1);
+                    const Block4 r1 = coin_block(q_first + j + 1, sc, k0, k1);
+                    const Block4 r2 = coin_block(q_first + j + 2, sc, k0, k1);
+                    const Block4 r3 = coin_block(q_first + j + 3, sc, k0, k1);
+                    live |= (live_bits(r0, thr_of(j)) | (live_bits(r1, thr_of(j + 1)) << 4) |
+                             (live_bits(r2, thr_of(j + 2)) << 8) | (live_bits(r3, thr_of(j + 3)) << 12))
+                            << (4 * j);
+                }
             } else {
                 live = 0;
                 for (uint32_t j = 0; j < nq; j += 2) {
