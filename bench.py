@@ -48,12 +48,14 @@ WORKLOADS = {
                         cpu_stride=1),
 }
 
-# ALU roofline of one Philox4x32-10 block on gfx950: the compiler emits 40
-# v_mul_hi/lo_u32 and 40 v_xor_b32 per block plus ~8 compare/select for the
-# four coins, all at the full vector issue rate (a Philox-only kernel reaches
-# 96% of this figure), against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+# ALU roofline of one Philox4x32-10 block on gfx950: per round two
+# v_mul_hi_u32, two v_mul_lo_u32 and two three-way xors (one v_bitop3_b32
+# each), so 40 multiplies + 20 logic instructions per block, plus ~8
+# compare/select for the four coins, all at the full vector issue rate (a
+# Philox-only kernel reaches 96% of this figure), against 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz.
 LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-SLOTS_PER_BLOCK = 40 + 40 + 8
+SLOTS_PER_BLOCK = 40 + 20 + 8
 PEAK_PHILOX_BLOCKS = LANE_SLOTS_PER_S / SLOTS_PER_BLOCK
 
 KERNEL_SOURCES = ["paper_2311_10201_amd/csrc/bpt_fused.hip", "paper_2311_10201_amd/csrc/bpt_rng.hpp",
