@@ -247,6 +247,99 @@ def order_study(out_path: str) -> int:
     return 0
 
 
+def plan_study(out_path: str) -> int:
+    """Per-call cost of the host-synchronous call (bpt_sample_rrr_device)
+    against a plan (bpt_plan_enqueue) run eagerly and as a captured hipGraph,
+    for a one-batch call (64 samples) and the R-MAT 20 workload.  Every path's
+    sets are compared with the host-synchronous call's."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2311_10201_amd as bpt
+
+    torch.cuda.set_device(0)
+    cases = []
+    src, dst = graphgen.er_graph(1000, 10_000, seed=42)
+    cases.append(("ER n=1,000 m=10,000 p=0.1", 1000, src, dst, graphgen.uniform_prob(len(src), 0.1), 64, 64, 400))
+    src, dst = graphgen.rmat_graph(20, 16, 0.57, 0.19, 0.19, seed=20)
+    cases.append(("R-MAT 20 WC", 1 << 20, src, dst, graphgen.wc_prob(1 << 20, dst), 100_000, 64, 20))
+    rows = []
+    for name, n, src, dst, prob, S, C, reps in cases:
+        g = bpt.bpt_create_graph(n, src, dst, prob)
+        stream = torch.cuda.Stream()
+        off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+        cap = max(1024, 64 * S)
+        vert = torch.empty(cap, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(stream):
+            st, total, _ = bpt.bpt_sample_rrr_device(g, 0, S, C, 42, 0, stream, off, vert, cap)
+        assert st == bpt.BPT_OK
+        ref_off, ref_vert = off.cpu().clone(), vert[:total].cpu().clone()
+
+        def timed(fn, sync_each):
+            for _ in range(3):
+                fn()
+            stream.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+                if sync_each:
+                    stream.synchronize()
+            stream.synchronize()
+            return (time.perf_counter() - t) / reps * 1e6
+
+        def device_call():
+            st_, _, _ = bpt.bpt_sample_rrr_device(g, 0, S, C, 42, 0, stream, off, vert, cap)
+            assert st_ == bpt.BPT_OK
+
+        plan = bpt.bpt_plan_create(g, S, C, 0)
+        res = torch.zeros(2, dtype=torch.int64, device="cuda")
+        params = torch.tensor([0, 42], dtype=torch.int64, device="cuda")
+
+        def plan_call():
+            bpt.bpt_plan_enqueue(plan, 0, S, 42, params, stream, off, vert, cap, res)
+
+        def check(what):
+            stream.synchronize()
+            status, members = res.cpu().tolist()
+            assert status == bpt.BPT_OK and members == total, (what, status, members, total)
+            assert torch.equal(off.cpu(), ref_off) and torch.equal(vert[:total].cpu(), ref_vert), what
+
+        row = dict(case=name, samples=S, colors=C, reps=reps)
+        row["device_call_us"] = timed(device_call, True)
+        with torch.cuda.stream(stream):
+            row["plan_eager_us"] = timed(plan_call, True)
+            check("plan eager")
+            row["plan_eager_pipelined_us"] = timed(plan_call, False)
+            check("plan eager, pipelined")
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream, capture_error_mode="thread_local"):
+            plan_call()
+        with torch.cuda.stream(stream):
+            res.zero_()
+            row["graph_replay_us"] = timed(graph.replay, True)
+            check("graph replay")
+            row["graph_replay_pipelined_us"] = timed(graph.replay, False)
+            check("graph replay, pipelined")
+        log(f"plan study: {name}: " + ", ".join(f"{k} {v:.1f}" for k, v in row.items() if k.endswith("_us")))
+        rows.append(row)
+        del graph
+        plan.close()
+        bpt.bpt_free(g)
+        del vert, off
+        torch.cuda.empty_cache()
+    with open(out_path, "w") as f:
+        json.dump(rows, f)
+    print("| call | samples | host-synchronous call | plan, eager | plan, eager, pipelined | graph replay | "
+          "graph replay, pipelined |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {r['case']} | {r['samples']} | {r['device_call_us']:.1f} us | {r['plan_eager_us']:.1f} us | "
+              f"{r['plan_eager_pipelined_us']:.1f} us | {r['graph_replay_us']:.1f} us | "
+              f"{r['graph_replay_pipelined_us']:.1f} us |")
+    return 0
+
+
 def mix_instances(w):
     """The seeded draw of the mix's instances (shapes only; graphs come later)."""
     import math
@@ -580,6 +673,9 @@ def main() -> int:
                     help="rmat-mix32: choose each instance's colours with bpt_tune_colors (untimed)")
     ap.add_argument("--order-study", default="", metavar="OUT.json",
                     help="instead of the benchmark: id-order vs sorted-start vs RCM-sorted batches")
+    ap.add_argument("--plan-study", default="", metavar="OUT.json",
+                    help="instead of the benchmark: per-call cost of the host-synchronous call vs a plan, eager "
+                         "and captured into a hipGraph")
     ap.add_argument("--fusion-study", default="", metavar="OUT.json",
                     help="instead of the benchmark: edge accesses and colour occupancy of the fused traversal "
                          "vs colour count and probability on LFR graphs; writes the records to OUT.json")
@@ -595,6 +691,8 @@ def main() -> int:
         return fusion_study(args.fusion_study)
     if args.order_study:
         return order_study(args.order_study)
+    if args.plan_study:
+        return plan_study(args.plan_study)
 
     import numpy as np
     import torch

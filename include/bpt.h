@@ -155,8 +155,9 @@ typedef struct bpt_job {
 bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_batch,
                         uint64_t seed);
 
-/* Frees a bpt_graph or a bpt_rrr (the handle carries its type).  NULL is a
- * no-op.  Sets BPT_EINVAL if the handle is not one of the two. */
+/* Frees a bpt_graph, a bpt_rrr or a bpt_plan (the handle carries its type).
+ * NULL is a no-op.  Sets BPT_EINVAL if the handle is none of these.  Free a
+ * plan only when no call on it is in flight, and before its graph. */
 void bpt_free(void* handle);
 
 /* Accessors of a result.  offsets has num_samples+1 entries; the members of
@@ -248,6 +249,58 @@ int bpt_graph_release_cache(bpt_graph* g);
  * or BPT_ENOMEM, BPT_EDEVICE, BPT_EINTERNAL.
  * ---------------------------------------------------------------------- */
 int bpt_sample_rrr_jobs(bpt_job* jobs, uint32_t n_jobs, void* stream, bpt_counters* counters);
+
+/* ------------------------------------------------------------------------
+ * Sampling plans: the fused path as a fixed sequence of kernels that can be
+ * captured into a hipGraph and replayed (the batches of paper Section 4.1's
+ * persistent launch, without a host round trip per call).
+ *
+ * bpt_plan_create reserves, once, everything a call of up to max_samples
+ * samples at colors_per_batch colours needs on graph g: traversal slots, a
+ * member pool of pool_capacity entries, per-sample arrays and a control
+ * block.  colors_per_batch 0 takes bpt_default_colors(g, max_samples);
+ * pool_capacity 0 takes an estimate from the graph's earlier calls (or 32
+ * members per sample).  Returns NULL on error: BPT_EINVAL (NULL graph,
+ * max_samples 0 or >= 2^34, bad colors_per_batch), BPT_ENOMEM, BPT_EDEVICE.
+ * The graph must outlive the plan.  Free with bpt_free().
+ * ---------------------------------------------------------------------- */
+typedef struct bpt_plan bpt_plan;
+
+bpt_plan* bpt_plan_create(bpt_graph* g, uint64_t max_samples, uint32_t colors_per_batch,
+                          uint64_t pool_capacity);
+
+/* bpt_plan_enqueue - enqueue the sampling of sets first_sample ..
+ * first_sample + n_samples - 1 on `stream` and return at once.  The call
+ * allocates nothing, launches only kernels (no memset or copy nodes) and never
+ * waits on the host, so it may run inside hipStreamBeginCapture /
+ * hipStreamEndCapture; each replay of the captured graph samples again.
+ *
+ *   n_samples    1 .. max_samples of the plan (0 writes an empty result).
+ *   d_params     NULL, or device memory holding two uint64 {first_sample,
+ *                seed}, read when the stream reaches the call (they override
+ *                the two arguments): a captured graph then samples whatever
+ *                range and seed the caller has written there, in stream order,
+ *                before each replay.  Ranges past 2^34 report BPT_EINVAL.
+ *   d_offsets    device array of n_samples+1 uint64 (CSR offsets).
+ *   d_vertices   device array of `capacity` uint32 (members, as in
+ *                bpt_sample_rrr_device); untouched when they do not fit.
+ *   d_result     device (or mapped pinned host) array of two int64 written at
+ *                the end: {status, members}.  status BPT_OK: members = total
+ *                written.  BPT_ERANGE: capacity too small (members = the total
+ *                needed, d_offsets valid) or the plan's pool too small
+ *                (members = pool entries needed: create a larger plan).
+ *                BPT_EINVAL: the range from d_params leaves [0, 2^34).
+ *                BPT_EINTERNAL: a device consistency check failed.
+ *
+ * The sets equal bpt_sample_rrr_device's for the same graph, range, seed and
+ * colours.  Calls on one plan must not overlap in time (one stream, or
+ * ordered streams): they share its workspace.  Returns BPT_OK when enqueued;
+ * BPT_EINVAL (bad handle or pointers, n_samples above the plan's maximum, a
+ * host-given range past 2^34) or BPT_EDEVICE, with nothing enqueued.
+ */
+int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uint64_t seed,
+                     const uint64_t* d_params, void* stream, uint64_t* d_offsets, uint32_t* d_vertices,
+                     uint64_t capacity, int64_t* d_result);
 
 /* ------------------------------------------------------------------------
  * bpt_max_cover - influence-maximization seeds from sampled RRR sets (paper

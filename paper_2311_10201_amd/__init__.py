@@ -21,7 +21,7 @@ __all__ = [
     "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED", "BPT_FLAG_SORTED_STARTS",
     "BptError", "Counters", "Graph", "Job", "RRRResult", "Request", "Server", "BPT_REQ_SAMPLE", "BPT_REQ_SEEDS",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
-    "bpt_max_cover",
+    "bpt_max_cover", "Plan", "bpt_plan_create", "bpt_plan_enqueue",
     "bpt_graph_info", "bpt_graph_set_vertex_order",
     "bpt_graph_release_cache",
     "bpt_default_colors", "bpt_tune_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
@@ -51,7 +51,7 @@ EXPORTED_SYMBOLS = (
     "bpt_graph_info", "bpt_graph_release_cache", "bpt_default_colors", "bpt_tune_colors", "bpt_thr32",
     "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs", "bpt_max_cover",
     "bpt_server_create", "bpt_server_submit", "bpt_server_wait", "bpt_server_now", "bpt_server_stats",
-    "bpt_server_destroy", "bpt_graph_set_vertex_order",
+    "bpt_server_destroy", "bpt_graph_set_vertex_order", "bpt_plan_create", "bpt_plan_enqueue",
 )
 
 
@@ -220,6 +220,8 @@ def load_library():
         "bpt_sample_rrr_device": (i32, [vp, u64, u64, u32, u64, u32, vp, vp, vp, u64,
                                         ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
         "bpt_sample_rrr_jobs": (i32, [ctypes.POINTER(_Job), u32, vp, ctypes.POINTER(_Counters)]),
+        "bpt_plan_create": (vp, [vp, u64, u32, u64]),
+        "bpt_plan_enqueue": (i32, [vp, u64, u64, u64, vp, vp, vp, vp, u64, vp]),
         "bpt_max_cover": (i32, [vp, vp, u64, u32, u32, vp, vp, vp]),
         "bpt_server_create": (vp, [u64, u32]),
         "bpt_server_submit": (i32, [vp, ctypes.POINTER(_Request)]),
@@ -390,6 +392,45 @@ def bpt_sample_rrr_jobs(jobs, stream=None):
         j.total = int(arr[i].total)
         j.status = int(arr[i].status)
     return st, Counters(**{k: int(getattr(cnt, k)) for k, _ in _Counters._fields_})
+
+
+class Plan:
+    """Owns a bpt_plan handle (a capturable sampling setup of one graph)."""
+
+    def __init__(self, handle: int, graph: Graph, max_samples: int):
+        self.handle = handle
+        self.graph = graph  # the graph must outlive the plan
+        self.max_samples = max_samples
+
+    def close(self):
+        if self.handle:
+            load_library().bpt_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bpt_plan_create(graph: Graph, max_samples: int, colors_per_batch: int = 0, pool_capacity: int = 0) -> Plan:
+    lib = load_library()
+    h = lib.bpt_plan_create(graph.handle, max_samples, colors_per_batch, pool_capacity)
+    if not h:
+        _raise_last()
+    return Plan(h, graph, max_samples)
+
+
+def bpt_plan_enqueue(plan: Plan, first_sample: int, n_samples: int, seed: int, d_params, stream, d_offsets,
+                     d_vertices, capacity: int, d_result) -> None:
+    """Enqueues one sampling call on `stream` (kernels only; capturable).  The
+    outcome {status, members} lands in the int64 device buffer d_result."""
+    st = load_library().bpt_plan_enqueue(plan.handle, first_sample, n_samples, seed, _addr(d_params),
+                                         _stream(stream), _addr(d_offsets), _addr(d_vertices), capacity,
+                                         _addr(d_result))
+    if st != BPT_OK:
+        _raise_last()
 
 
 def bpt_max_cover(d_offsets, d_vertices, n_sets: int, n: int, k: int, stream=None):

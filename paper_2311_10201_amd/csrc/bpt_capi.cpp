@@ -22,6 +22,7 @@ namespace {
 
 constexpr uint32_t kGraphMagic = 0x42505447u;  // "BPTG"
 constexpr uint32_t kRrrMagic = 0x42505452u;    // "BPTR"
+constexpr uint32_t kPlanMagic = 0x4250504Cu;   // "BPPL"
 constexpr uint32_t kDeadMagic = 0xDEADBEEFu;
 
 thread_local int t_status = BPT_OK;
@@ -141,6 +142,18 @@ struct bpt_graph {
     uint32_t tuned[64] = {};  // colours measured fastest for jobs of 2^i .. 2^(i+1)-1 samples (0: none)
     double mean_members = 0;  // running mean set size of this graph's calls (0: none yet), sizes pools
     uint32_t* d_rank = nullptr;  // vertex order for sorted starts (null: vertex ids)
+};
+
+// A reusable, capturable sampling setup: a private workspace with its pool and
+// per-sample arrays, and a one-entry device job table that the setup kernel
+// fills at run time.
+struct bpt_plan {
+    uint32_t magic;
+    bpt_graph* graph;
+    bpt::Workspace* ws;
+    bpt::FusedJob* d_job;
+    uint64_t max_samples;
+    uint32_t colors;
 };
 
 struct bpt_rrr {
@@ -1169,6 +1182,116 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
     return r;
 }
 
+bpt_plan* bpt_plan_create(bpt_graph* g, uint64_t max_samples, uint32_t colors_per_batch, uint64_t pool_capacity) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return nullptr;
+    }
+    if (max_samples == 0 || max_samples >= kMaxSamples) {
+        set_status(BPT_EINVAL, "max_samples must be in [1, 2^34)");
+        return nullptr;
+    }
+    const uint32_t colors = colors_per_batch ? colors_per_batch : choose_colors(gg, max_samples);
+    if (!valid_colors(colors)) {
+        set_status(BPT_EINVAL, "colors_per_batch must be 0 or a power of two from 8 to 1024");
+        return nullptr;
+    }
+    bpt_plan* p = nullptr;
+    try {
+        HIP_TRY(hipSetDevice(gg->device));
+        p = new bpt_plan();
+        p->magic = kDeadMagic;  // until complete
+        p->graph = gg;
+        p->max_samples = max_samples;
+        p->colors = colors;
+        const int nw = mask_words(colors);
+        p->ws = make_workspace(gg, nw, (max_samples + colors - 1) / colors);
+        ensure_sample_arrays(p->ws, max_samples);
+        ensure_pool(gg, p->ws, pool_capacity ? pool_capacity : pool_estimate(gg, max_samples));
+        p->d_job = dev_alloc<FusedJob>(1);
+        FusedJob j = {};
+        j.g = dev_graph(gg);
+        j.colors = colors;
+        HIP_TRY(hipMemcpy(p->d_job, &j, sizeof(j), hipMemcpyHostToDevice));
+        HIP_TRY(hipDeviceSynchronize());
+        p->magic = kPlanMagic;
+    } catch (const HipFail& f) {
+        if (p) {
+            delete p->ws;
+            dev_free(p->d_job);
+            delete p;
+        }
+        set_status(f.status, f.msg);
+        return nullptr;
+    } catch (const std::bad_alloc&) {
+        if (p) {
+            delete p->ws;
+            dev_free(p->d_job);
+            delete p;
+        }
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    set_ok();
+    return p;
+}
+
+int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uint64_t seed, const uint64_t* d_params,
+                     void* stream, uint64_t* d_offsets, uint32_t* d_vertices, uint64_t capacity, int64_t* d_result) {
+    if (!p || p->magic != kPlanMagic) {
+        set_status(BPT_EINVAL, "not a bpt_plan handle");
+        return BPT_EINVAL;
+    }
+    if (!d_offsets || !d_result || (!d_vertices && capacity > 0)) {
+        set_status(BPT_EINVAL, "d_offsets and d_result are required (d_vertices when capacity > 0)");
+        return BPT_EINVAL;
+    }
+    if (n_samples > p->max_samples) {
+        set_status(BPT_EINVAL, "n_samples exceeds the plan's max_samples (" + std::to_string(p->max_samples) + ")");
+        return BPT_EINVAL;
+    }
+    if (!d_params && (first_sample >= kMaxSamples || n_samples > kMaxSamples - first_sample)) {
+        set_status(BPT_EINVAL, "sample ids must stay below 2^34");
+        return BPT_EINVAL;
+    }
+    try {
+        HIP_TRY(hipSetDevice(p->graph->device));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Workspace* ws = p->ws;
+        HIP_TRY(launch_plan_setup(p->d_job, d_params, first_sample, seed, n_samples, kMaxSamples, ws->ctl, st));
+        if (n_samples > 0) {
+            FusedArgs a = {};
+            a.job0.g = dev_graph(p->graph);
+            a.job0.colors = p->colors;
+            a.job0.n_samples = n_samples;
+            a.jobs = p->d_job;  // range and seed are read from the device job the setup kernel wrote
+            a.n_jobs = 1;
+            a.n_max = p->graph->n;
+            a.ws = ws->fs;
+            a.out.counts = ws->counts;
+            a.out.where = ws->where;
+            a.out.pool = ws->pool;
+            a.out.pool_cap = ws->pool_cap;
+            a.ctl = ws->ctl;
+            a.n_batches = (n_samples + p->colors - 1) / p->colors;
+            a.gather_mode = gather_mode();
+            int block = 0, grid = 0;
+            fused_launch_shape(p->graph, ws->nw, ws->slots, a.n_batches, &block, &grid);
+            HIP_TRY(launch_fused(a, ws->nw, block, grid, st));
+        }
+        HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, n_samples,
+                                reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity,
+                                &ws->ctl->total, &ws->ctl->err, ws->scratch, ws->scratch_bytes, st));
+        HIP_TRY(launch_plan_report(ws->ctl, capacity, d_result, st));
+    } catch (const HipFail& f) {
+        set_status(f.status, f.msg);
+        return f.status;
+    }
+    set_ok();
+    return BPT_OK;
+}
+
 void bpt_free(void* handle) {
     if (!handle) {
         set_ok();
@@ -1187,6 +1310,14 @@ void bpt_free(void* handle) {
         dev_free(g->d_thr_edge);
         dev_free(g->d_rank);
         delete g;
+        set_ok();
+    } else if (magic == kPlanMagic) {
+        bpt_plan* p = static_cast<bpt_plan*>(handle);
+        p->magic = kDeadMagic;
+        (void)hipSetDevice(p->graph->device);
+        delete p->ws;
+        dev_free(p->d_job);
+        delete p;
         set_ok();
     } else if (magic == kRrrMagic) {
         bpt_rrr* r = static_cast<bpt_rrr*>(handle);

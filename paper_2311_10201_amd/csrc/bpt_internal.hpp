@@ -41,6 +41,7 @@ enum ErrorBits : unsigned int {
     kErrPoolOverflow = 1u,   // output pool too small: grow and run again
     kErrQueueOverflow = 2u,  // frontier queue exceeded n entries (cannot happen)
     kErrLevelBound = 4u,     // more than n+1 levels in one batch (cannot happen)
+    kErrBadRange = 8u,       // a plan's device-supplied sample range leaves [0, 2^34)
 };
 
 // Small per-call control block in device memory.
@@ -140,6 +141,14 @@ constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, o
 size_t order_scratch_bytes(uint64_t n_samples, uint32_t n);
 hipError_t launch_sort_by_start(uint32_t n, uint64_t seed, uint64_t first, uint64_t n_samples, const uint32_t* rank,
                                 void* scratch, size_t scratch_bytes, const uint32_t** order, hipStream_t stream);
+
+// Plans (bpt_plan.hip): the kernels that open and close a capturable call.
+// plan_setup clears the control block and sets the job's sample range and
+// seed (from `params` = {first_sample, seed} in device memory when not null);
+// plan_report writes {status, members} for the caller once the CSR is built.
+hipError_t launch_plan_setup(FusedJob* job, const uint64_t* params, uint64_t first, uint64_t seed,
+                             uint64_t n_samples, uint64_t max_ids, Control* ctl, hipStream_t stream);
+hipError_t launch_plan_report(const Control* ctl, unsigned long long capacity, int64_t* result, hipStream_t stream);
 
 // Greedy maximum coverage (bpt_cover.hip).  Error bits of its device flag.
 constexpr unsigned int kCoverBadOffsets = 1u;  // offsets not non-decreasing or past the member count

@@ -121,3 +121,9 @@ def test_bad_handles_are_reported():
     total = ctypes.c_uint64(0)
     st = lib.bpt_sample_rrr_device(None, 0, 10, 64, 1, 0, None, None, None, 0, ctypes.byref(total), None)
     assert st == bpt.BPT_EINVAL
+    assert lib.bpt_plan_create(None, 10, 64, 0) is None
+    assert lib.bpt_last_status() == bpt.BPT_EINVAL
+    st = lib.bpt_plan_enqueue(None, 0, 10, 1, None, None, None, None, 0, None)
+    assert st == bpt.BPT_EINVAL
+    st = lib.bpt_plan_enqueue(ctypes.addressof(junk), 0, 10, 1, None, None, None, None, 0, None)
+    assert st == bpt.BPT_EINVAL
