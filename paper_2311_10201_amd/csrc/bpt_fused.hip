@@ -259,12 +259,18 @@ __device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
            (coin_live(r.w3, t.w) ? 8u : 0u);
 }
 
+// Words of a block below one threshold (the p = 1 sentinel is handled by the caller).
+__device__ __forceinline__ uint32_t below_bits(const Block4& r, uint32_t t) {
+    return (r.w0 < t ? 1u : 0u) | (r.w1 < t ? 2u : 0u) | (r.w2 < t ? 4u : 0u) | (r.w3 < t ? 8u : 0u);
+}
+
 // Coins of the work item's quads [q_first, q_end) (at most kQuadsPerItem) of
 // the row [beg, end) for every colour in `mask`, and discovery of the live
 // ones.  Two schedules, chosen per wavefront (FusedArgs::gather_mode):
 //  * mostly one colour per entry: the item's Philox blocks of a colour are
 //    independent and are evaluated side by side (in rounds of four when the
-//    mask is one word and any lane has more than two quads, else in pairs),
+//    mask is one word, the row has one threshold and any lane has more than
+//    two quads, else in pairs),
 //    so that a wavefront alone on its SIMD still keeps the multiplier
 //    pipeline busy; each live coin is discovered on its own;
 //  * several colours per entry: per (quad, mask word) the blocks of two
@@ -289,6 +295,9 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
     if (e_first < beg) valid &= 0xFFFFFFFFu << (beg - e_first);
     const bool per_edge = g.prob_layout == BPT_PROB_EDGE;
     const uint4 t_row = make_uint4(thr_row, thr_row, thr_row, thr_row);
+    // one threshold for the whole row: its p = 1 sentinel is tested once per item, and each
+    // coin costs one compare (per-edge thresholds test both conditions per coin)
+    const uint32_t row_always = (!per_edge && thr_row == kAlwaysLive) ? 0xFu : 0u;
     // thresholds of quad j of the item (per-edge layout: re-read per colour, an L1 hit)
     auto thr_of = [&](uint32_t j) -> uint4 {
         return (per_edge && j < nq) ? *reinterpret_cast<const uint4*>(g.thr_edge + e_first + 4 * j) : t_row;
@@ -344,8 +353,8 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
         return;
     }
 
-    // four side by side only where registers allow it (one colour word); two otherwise
-    const bool wide = (NW == 1) && __any(nq > 2);
+    // four side by side only where registers allow it (one colour word, one threshold per row); two otherwise
+    const bool wide = (NW == 1) && !per_edge && __any(nq > 2);
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
         unsigned long long mk = mask[k];
@@ -362,16 +371,20 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
                     const Block4 r1 = coin_block(q_first + j + 1, sc, k0, k1);
                     const Block4 r2 = coin_block(q_first + j + 2, sc, k0, k1);
                     const Block4 r3 = coin_block(q_first + j + 3, sc, k0, k1);
-                    live |= (live_bits(r0, thr_of(j)) | (live_bits(r1, thr_of(j + 1)) << 4) |
-                             (live_bits(r2, thr_of(j + 2)) << 8) | (live_bits(r3, thr_of(j + 3)) << 12))
-                            << (4 * j);
+                    live |= ((below_bits(r0, thr_row) | (below_bits(r1, thr_row) << 4) |
+                              (below_bits(r2, thr_row) << 8) | (below_bits(r3, thr_row) << 12)) |
+                             (row_always * 0x1111u)) << (4 * j);
                 }
             } else {
                 live = 0;
                 for (uint32_t j = 0; j < nq; j += 2) {
                     const Block4 r0 = coin_block(q_first + j, sc, k0, k1);
                     const Block4 r1 = coin_block(q_first + j + 1, sc, k0, k1);  // past the row: masked below
-                    live |= (live_bits(r0, thr_of(j)) | (live_bits(r1, thr_of(j + 1)) << 4)) << (4 * j);
+                    if (per_edge)
+                        live |= (live_bits(r0, thr_of(j)) | (live_bits(r1, thr_of(j + 1)) << 4)) << (4 * j);
+                    else
+                        live |= (below_bits(r0, thr_row) | (below_bits(r1, thr_row) << 4) | (row_always * 0x11u))
+                                << (4 * j);
                 }
             }
             n_philox += nq;
