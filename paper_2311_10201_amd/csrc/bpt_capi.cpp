@@ -233,6 +233,7 @@ size_t fused_slot_bytes(uint32_t n, int nw) {
     b += 2 * N * 4;         // queue
     b += N * 4;             // touched
     b += bitmap_words(n) * 8;  // touched bitmap
+    if (nw == 1) b += sizeof(HelpRec) + (size_t)kHelpStagePos * 6 * 4;  // help record and chunk staging
     return b;
 }
 
@@ -293,6 +294,10 @@ Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
             ws->fs.touched = reinterpret_cast<uint32_t*>(take(S * N * 4));
             ws->fs.tbits = reinterpret_cast<unsigned long long*>(take(S * words * 8));
             ws->fs.slot_tag = reinterpret_cast<uint32_t*>(take(S * 4));
+            if (nw == 1) {
+                ws->fs.help = reinterpret_cast<HelpRec*>(take(S * sizeof(HelpRec)));
+                ws->fs.hstage = reinterpret_cast<uint32_t*>(take(S * kHelpStagePos * 6 * 4));
+            }
             ws->fs.slots = ws->slots;
         } else {
             const size_t per = unfused_slot_bytes(n) + 512;
@@ -427,6 +432,19 @@ uint64_t pool_estimate(bpt_graph* g, uint64_t n_samples) {
     const double per = mean > 0 ? mean * 1.3 : 32.0;
     const double est = std::min<double>((double)n_samples * per, (double)g->n * (double)n_samples);
     return (uint64_t)est + 1024;
+}
+
+// Helping (idle workgroups joining the batches still running at the end of a
+// launch) pays when sets are large: batches have few, heavy levels and the
+// launch ends on a tail of them.  Deep traversals of small sets lose time to
+// it, so it is used once a graph's running mean set size reaches
+// kHelpMembers; BPT_HELP=0 or 1 forces it.
+constexpr double kHelpMembers = 1024.0;
+bool help_wanted(bpt_graph* g) {
+    const int forced = env_int("BPT_HELP", -1);
+    if (forced >= 0) return forced != 0;
+    std::lock_guard<std::mutex> lk(g->mu);
+    return g->mean_members >= kHelpMembers;
 }
 
 void note_members(bpt_graph* g, uint64_t n_samples, uint64_t total) {
@@ -571,7 +589,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.n_batches = (S + colors - 1) / colors;
             a.gather_mode = gather_mode();
             fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
-            HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
+            HIP_TRY(launch_fused(a, ws->nw, block, grid, help_wanted(g), stream));
         } else {
             UnfusedArgs a;
             a.g = dev_graph(g);
@@ -696,7 +714,9 @@ int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<u
         a.gather_mode = gather_mode();
         int block = 256, grid = 1;
         fused_launch_shape(owner, ws->nw, ws->slots, n_batches, &block, &grid);
-        HIP_TRY(launch_fused(a, ws->nw, block, grid, stream));
+        bool help = false;
+        for (uint32_t i = 0; i < J; ++i) help = help || help_wanted(jobs[live[i]].graph);
+        HIP_TRY(launch_fused(a, ws->nw, block, grid, help, stream));
         HIP_TRY(hipEventRecord(ws->ev[1], stream));
         for (uint32_t i = 0; i < J; ++i) {
             const bpt_job& jb = jobs[live[i]];
@@ -1278,7 +1298,7 @@ int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uin
             a.gather_mode = gather_mode();
             int block = 0, grid = 0;
             fused_launch_shape(p->graph, ws->nw, ws->slots, a.n_batches, &block, &grid);
-            HIP_TRY(launch_fused(a, ws->nw, block, grid, st));
+            HIP_TRY(launch_fused(a, ws->nw, block, grid, help_wanted(p->graph), st));
         }
         HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, n_samples,
                                 reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity,

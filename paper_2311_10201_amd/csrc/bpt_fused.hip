@@ -77,6 +77,15 @@ struct FusedShared {
     uint32_t tlen;
     unsigned long long batch;
     uint32_t job;
+    // helping (one-word masks): the owner's decision and the helpers' commands
+    uint32_t tail;     // the launch has no batch left to claim
+    uint32_t probes;   // heavy chunks seen before that
+    uint32_t go;       // this batch takes helpers from now on
+    uint32_t unit;     // unit of work items just claimed
+    uint32_t cmd;      // helper: what to do next
+    uint32_t pick;     // helper: offset of the slot to join
+    uint32_t h_npos, h_nxt, h_qnext;  // helper: the joined chunk's parameters
+    unsigned long long claimed;        // helper: value returned by its claim
     uint32_t scan_tmp[2][BS / kWave];
     unsigned long long base;
     unsigned long long stats[kNumStats];
@@ -171,6 +180,18 @@ __device__ __forceinline__ unsigned long long load_coherent64(const unsigned lon
 __device__ __forceinline__ void store_coherent64(unsigned long long* p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint32_t load_coherent32(const uint32_t* p) {
+    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Where a batch's discovery counters live: the owner's LDS while it runs the
+// batch alone, the slot's help record once other workgroups may join (then the
+// queue and touched entries are written coherently too).
+struct Ctr {
+    uint32_t* qlen;  // [3], indexed by level % 3
+    uint32_t* tlen;
+    uint32_t* cnt;   // [64 * NW]
+};
 
 // Traversal state of one slot.
 template <int NW>
@@ -210,8 +231,8 @@ __device__ __forceinline__ BatchCtx<NW> slot_ctx(const FusedArgs& a, uint32_t sl
 // (Listing 1's visited / frontier update, one atomic per mask word as in its
 // fusing OR, with the visited mark taken at discovery time).  `next` is the
 // parity of the level the new frontier entry belongs to, `qslot` its counter.
-template <int NW, int BS>
-__device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, FusedShared<NW, BS>& s, uint32_t u, int k,
+template <int NW, bool kSh>
+__device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, const Ctr& ct, uint32_t u, int k,
                                               unsigned long long bits, int next, uint32_t qslot, uint32_t tag,
                                               uint32_t base_tag) {
     const size_t idx = (size_t)u * NW + k;
@@ -221,7 +242,7 @@ __device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, FusedShared
     unsigned long long* fr = next ? b.frontier1 : b.frontier0;
     const unsigned long long old_next = atomicOr(&fr[idx], fresh);
     for (unsigned long long f = fresh; f; f &= f - 1)
-        atomicAdd(&s.cnt[k * 64 + (__ffsll((long long)f) - 1)], 1u);
+        atomicAdd(&ct.cnt[k * 64 + (__ffsll((long long)f) - 1)], 1u);
     bool push, first;
     if constexpr (NW == 1) {
         (void)tag;
@@ -235,23 +256,26 @@ __device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, FusedShared
         first = st < base_tag;
     }
     if (push) {
-        const uint32_t pos = atomicAdd(&s.qlen[qslot], 1u);
-        if (pos < b.n) (next ? b.queue1 : b.queue0)[pos] = u;
-        else atomicOr(b.err, (unsigned)kErrQueueOverflow);
+        const uint32_t pos = atomicAdd(&ct.qlen[qslot], 1u);
+        uint32_t* q = next ? b.queue1 : b.queue0;
+        if (pos >= b.n) atomicOr(b.err, (unsigned)kErrQueueOverflow);
+        else if constexpr (kSh) store_coherent(&q[pos], u);
+        else q[pos] = u;
     }
     if (first) {
         atomicOr(&b.tbits[u >> 6], 1ull << (u & 63));  // result unused: no wait
-        const uint32_t pos = atomicAdd(&s.tlen, 1u);
-        if (pos < b.n) b.touched[pos] = u;
-        else atomicOr(b.err, (unsigned)kErrQueueOverflow);
+        const uint32_t pos = atomicAdd(ct.tlen, 1u);
+        if (pos >= b.n) atomicOr(b.err, (unsigned)kErrQueueOverflow);
+        else if constexpr (kSh) store_coherent(&b.touched[pos], u);
+        else b.touched[pos] = u;
     }
 }
 
 // (u, c) became reachable (one colour).
-template <int NW, int BS>
-__device__ __forceinline__ void discover(const BatchCtx<NW>& b, FusedShared<NW, BS>& s, uint32_t u, uint32_t c,
+template <int NW, bool kSh>
+__device__ __forceinline__ void discover(const BatchCtx<NW>& b, const Ctr& ct, uint32_t u, uint32_t c,
                                          int next, uint32_t qslot, uint32_t tag, uint32_t base_tag) {
-    discover_word<NW, BS>(b, s, u, (int)(c >> 6), 1ull << (c & 63), next, qslot, tag, base_tag);
+    discover_word<NW, kSh>(b, ct, u, (int)(c >> 6), 1ull << (c & 63), next, qslot, tag, base_tag);
 }
 
 __device__ __forceinline__ uint32_t live_bits(const Block4& r, const uint4& t) {
@@ -277,15 +301,14 @@ __device__ __forceinline__ uint32_t below_bits(const Block4& r, uint32_t t) {
 //    colours are evaluated side by side and each edge's live colours are
 //    gathered into one mask, so visited[u] and the next frontier take one
 //    atomic per (edge, word) whatever the number of colours (Listing 1).
-template <int NW, int BS>
+template <int NW, int BS, bool kSh>
 __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, uint32_t gather_mode,
-                                            const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
+                                            const BatchCtx<NW>& b, FusedShared<NW, BS>& s, const Ctr& ct,
                                             const unsigned long long (&mask)[NW], unsigned long long s0,
                                             unsigned long long first, bool ordered,
                                             uint32_t beg, uint32_t end, uint32_t thr_row, uint32_t q_first,
                                             uint32_t q_end, int nxt, uint32_t qslot, uint32_t tag,
-                                            uint32_t base_tag, unsigned long long& n_philox,
-                                            unsigned long long& n_live) {
+                                            uint32_t base_tag, uint32_t& n_philox, uint32_t& n_live) {
     static_assert(kQuadsPerItem % 4 == 0 && kQuadsPerItem <= 8, "an item's coin words must fit 32 bits");
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t nq = q_end - q_first;
@@ -344,10 +367,10 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
                     acc3 |= ((l0 & 8u) ? m0 : 0ull) | ((l1 & 8u) ? m1 : 0ull);
                 }
                 const uint32_t e0 = quad << 2;
-                if (acc0) { n_live += __popcll(acc0); discover_word<NW, BS>(b, s, g.col[e0], k, acc0, nxt, qslot, tag, base_tag); }
-                if (acc1) { n_live += __popcll(acc1); discover_word<NW, BS>(b, s, g.col[e0 + 1], k, acc1, nxt, qslot, tag, base_tag); }
-                if (acc2) { n_live += __popcll(acc2); discover_word<NW, BS>(b, s, g.col[e0 + 2], k, acc2, nxt, qslot, tag, base_tag); }
-                if (acc3) { n_live += __popcll(acc3); discover_word<NW, BS>(b, s, g.col[e0 + 3], k, acc3, nxt, qslot, tag, base_tag); }
+                if (acc0) { n_live += __popcll(acc0); discover_word<NW, kSh>(b, ct, g.col[e0], k, acc0, nxt, qslot, tag, base_tag); }
+                if (acc1) { n_live += __popcll(acc1); discover_word<NW, kSh>(b, ct, g.col[e0 + 1], k, acc1, nxt, qslot, tag, base_tag); }
+                if (acc2) { n_live += __popcll(acc2); discover_word<NW, kSh>(b, ct, g.col[e0 + 2], k, acc2, nxt, qslot, tag, base_tag); }
+                if (acc3) { n_live += __popcll(acc3); discover_word<NW, kSh>(b, ct, g.col[e0 + 3], k, acc3, nxt, qslot, tag, base_tag); }
             }
         }
         return;
@@ -393,7 +416,7 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
                 const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
                 live &= live - 1;
                 ++n_live;
-                discover<NW, BS>(b, s, g.col[e_first + j], c, nxt, qslot, tag, base_tag);
+                discover<NW, kSh>(b, ct, g.col[e_first + j], c, nxt, qslot, tag, base_tag);
             }
         }
     }
@@ -409,6 +432,35 @@ __device__ __forceinline__ uint32_t find_entry(const uint32_t* scan, uint32_t cn
     }
     return lo;
 }
+
+// Work item t of the chunk staged in LDS (npos positions).
+template <int NW, int BS, bool kSh>
+__device__ __forceinline__ void run_item(const DevGraph& g, uint64_t seed, uint32_t gather_mode, const BatchCtx<NW>& b,
+                                         FusedShared<NW, BS>& s, const Ctr& ct, unsigned long long s0,
+                                         unsigned long long first, bool ordered, uint32_t t, uint32_t npos, int nxt,
+                                         uint32_t qnext, uint32_t tag, uint32_t base_tag,
+                                         uint32_t& th_philox, uint32_t& th_live) {
+    const uint32_t i = find_entry(s.u.st.scan, npos, t);
+    const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
+    const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * kQuadsPerItem;
+    const uint32_t q_end = min(q_first + kQuadsPerItem, ((end - 1) >> 2) + 1);
+    unsigned long long mask[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
+    expand_item<NW, BS, kSh>(g, seed, gather_mode, b, s, ct, mask, s0, first, ordered, beg, end, s.u.st.thr[i],
+                             q_first, q_end, nxt, qnext, tag, base_tag, th_philox, th_live);
+}
+
+// Helping: a chunk is published when it has at least kHelpMin work items; a
+// unit is BS consecutive items.  claim = [63:48] chunk number, [47:20] items,
+// [19:0] next unit.
+constexpr uint32_t kHelpMinUnits = 4;
+__device__ __forceinline__ uint32_t claim_seq(unsigned long long c) { return (uint32_t)(c >> 48); }
+__device__ __forceinline__ uint32_t claim_items(unsigned long long c) { return (uint32_t)(c >> 20) & 0x0FFFFFFFu; }
+__device__ __forceinline__ uint32_t claim_unit(unsigned long long c) { return (uint32_t)c & 0xFFFFFu; }
+constexpr uint32_t kWaitSpins = 1u << 26;   // owner: bound of the wait for helpers (never reached)
+constexpr uint32_t kPollRounds = 1u << 15;  // helper: idle polls before it gives up on a batch
+constexpr uint32_t kIdleRounds = 1u << 15;  // helper: rounds without an open batch before it stops
 
 // Writes each colour's members (ascending) from the sorted vertex list
 // `list[0..T)` into the pool and clears visited[] for the listed vertices.
@@ -496,7 +548,166 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
     return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
 }
 
+// The job data of launch-wide batch bt (of job `job`), in scalar registers.
+struct BatchJob {
+    DevGraph g;
+    uint64_t seed, first, n_samples, out_base;
+    uint64_t batch;  // index within the job
+    uint32_t colors;
+    const uint32_t* order;
+};
+
+__device__ __forceinline__ BatchJob batch_job(const FusedArgs& a, uint32_t job, unsigned long long bt) {
+    const FusedJob* jp = a.jobs ? a.jobs + uni32(job) : nullptr;
+    BatchJob j;
+    j.g.rowptr = uni_ptr(jp ? jp->g.rowptr : a.job0.g.rowptr);
+    j.g.col = uni_ptr(jp ? jp->g.col : a.job0.g.col);
+    j.g.thr_row = uni_ptr(jp ? jp->g.thr_row : a.job0.g.thr_row);
+    j.g.thr_edge = uni_ptr(jp ? jp->g.thr_edge : a.job0.g.thr_edge);
+    j.g.thr_uniform = uni32(jp ? jp->g.thr_uniform : a.job0.g.thr_uniform);
+    j.g.prob_layout = uni32(jp ? jp->g.prob_layout : a.job0.g.prob_layout);
+    j.g.n = uni32(jp ? jp->g.n : a.job0.g.n);
+    j.g.m = uni32(jp ? jp->g.m : a.job0.g.m);
+    j.seed = uni64(jp ? jp->seed : a.job0.seed);
+    j.first = uni64(jp ? jp->first_sample : a.job0.first_sample);
+    j.n_samples = uni64(jp ? jp->n_samples : a.job0.n_samples);
+    j.out_base = uni64(jp ? jp->out_base : a.job0.out_base);
+    j.colors = uni32(jp ? jp->colors : a.job0.colors);
+    j.order = uni_ptr(jp ? jp->order : a.job0.order);
+    j.batch = uni64(bt) - uni64(jp ? jp->batch_begin : a.job0.batch_begin);
+    return j;
+}
+
+// Once no batch is left to claim, a workgroup helps batches still running
+// (one-word masks): it joins an open one (the first after its own slot),
+// claims units of the chunks its owner publishes and expands them as the owner
+// would, with the batch's counters in the help record.  It leaves when the
+// batch closes and stops when every batch is finished; owners never wait for
+// a helper that has not claimed work, so a helper may also give up at any
+// time between claims.
 template <int NW, int BS>
+__device__ void help_others(const FusedArgs& a, FusedShared<NW, BS>& s, uint32_t& th_philox, uint32_t& th_live) {
+    constexpr uint32_t kChunkPos = BS * ept(NW, BS);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t grid = gridDim.x;
+    uint32_t idle = 0, nap = 1;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {  // 0: look for an open batch, 1: stop, 2: nothing open yet
+            s.pick = kNone;
+            if (load_coherent64(&a.ctl->finished) >= a.n_batches || ++idle > kIdleRounds) s.cmd = 1u;
+            else s.cmd = load_coherent64(&a.ctl->open) ? 0u : 2u;
+        }
+        __syncthreads();
+        if (s.cmd == 1u) return;
+        if (s.cmd == 0u) {
+            for (uint32_t off = tid + 1; off < grid; off += BS) {
+                if (load_coherent32(&a.ws.help[(blockIdx.x + off) % grid].state) == 1u) {
+                    atomicMin(&s.pick, off);
+                    break;
+                }
+            }
+            __syncthreads();
+        }
+        if (s.pick == kNone) {  // back off (up to ~50 us between looks)
+            for (uint32_t i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(127);
+            nap = min(2u * nap, 16u);
+            continue;
+        }
+        nap = 1;
+        const uint32_t h = (blockIdx.x + s.pick) % grid;
+        HelpRec* const hr = a.ws.help + h;
+        if (tid == 0) {
+            s.batch = load_coherent64(&hr->batch);
+            s.job = load_coherent32(&hr->job);
+        }
+        __syncthreads();
+        if (s.batch >= a.n_batches || (a.jobs && s.job >= a.n_jobs)) continue;
+        const BatchJob jb = batch_job(a, s.job, s.batch);
+        BatchCtx<NW> b = slot_ctx<NW>(a, h);
+        b.n = jb.g.n;
+        const unsigned long long s0 = jb.first + jb.batch * jb.colors;
+        const Ctr ct{hr->qlen, &hr->tlen, s.cnt};  // colour counts kept here, added to hr->cnt per unit
+        for (uint32_t c = tid; c < 64u; c += BS) s.cnt[c] = 0u;
+        const uint32_t* stage = a.ws.hstage + (size_t)h * kHelpStagePos * 6;
+        uint32_t have = 0, spent = 0, polls = 0, wait = 1;  // staged chunk; exhausted chunk (thread 0)
+        for (;;) {
+            if (tid == 0) {
+                uint32_t cmd = 0;  // 0: wait, 1: leave, 2: expand the claimed unit
+                unsigned long long r = 0;
+                if (load_coherent32(&hr->state) != 1u) {
+                    cmd = 1;
+                } else {
+                    const unsigned long long c = load_coherent64(&hr->claim);
+                    if (claim_seq(c) != 0 && claim_seq(c) != spent &&
+                        (unsigned long long)claim_unit(c) * BS < claim_items(c)) {
+                        r = atomicAdd(&hr->claim, 1ull);
+                        if ((unsigned long long)claim_unit(r) * BS < claim_items(r)) cmd = 2;
+                        else spent = claim_seq(r);
+                    }
+                }
+                s.cmd = cmd;
+                s.claimed = r;
+            }
+            __syncthreads();
+            const uint32_t cmd = s.cmd;
+            const unsigned long long r = s.claimed;
+            __syncthreads();
+            if (cmd == 1) break;
+            if (cmd == 0) {  // the owner has not published its next chunk yet
+                if (++polls > kPollRounds) break;
+                for (uint32_t i = 0; i < wait; ++i) __builtin_amdgcn_s_sleep(16);
+                wait = min(2u * wait, 8u);
+                continue;
+            }
+            polls = 0;
+            wait = 1;
+            if (claim_seq(r) != have) {  // the chunk's staging: valid while our unit is unfinished
+                if (tid == 0) {
+                    s.h_npos = min(load_coherent32(&hr->npos), kChunkPos);
+                    s.h_nxt = load_coherent32(&hr->nxt);
+                    s.h_qnext = load_coherent32(&hr->qnext);
+                }
+                __syncthreads();
+                const uint32_t npos = s.h_npos;
+                for (uint32_t p = tid; p < npos; p += BS) {
+                    s.u.st.scan[p] = load_coherent32(stage + p);
+                    const uint32_t end = min(load_coherent32(stage + 2 * kHelpStagePos + p), jb.g.m);
+                    s.u.st.beg[p] = min(load_coherent32(stage + kHelpStagePos + p), end);
+                    s.u.st.end[p] = end;
+                    s.u.st.thr[p] = load_coherent32(stage + 3 * kHelpStagePos + p);
+                    s.u.st.mask[p][0] = (unsigned long long)load_coherent32(stage + 4 * kHelpStagePos + p) |
+                                        ((unsigned long long)load_coherent32(stage + 5 * kHelpStagePos + p) << 32);
+                }
+                __syncthreads();
+                have = claim_seq(r);
+            }
+            const uint32_t total = claim_items(r), unit = claim_unit(r);
+            const uint32_t t = unit * BS + tid;
+            if (t < total)
+                run_item<NW, BS, true>(jb.g, jb.seed, a.gather_mode, b, s, ct, s0, jb.first, false, t, s.h_npos,
+                                       (int)s.h_nxt, s.h_qnext, 0u, 0u, th_philox, th_live);
+            if (th_philox >= 0x80000000u || th_live >= 0x80000000u) {
+                atomicAdd(&s.stats[kStatPhilox], (unsigned long long)th_philox);
+                atomicAdd(&s.stats[kStatLive], (unsigned long long)th_live);
+                th_philox = th_live = 0;
+            }
+            wait_own_memory_ops();  // discoveries and queue entries performed before they are counted
+            __syncthreads();
+            for (uint32_t c = tid; c < 64u; c += BS) {
+                if (s.cnt[c]) atomicAdd(&hr->cnt[c], s.cnt[c]);
+                s.cnt[c] = 0u;
+            }
+            wait_own_memory_ops();
+            __syncthreads();
+            if (tid == 0) atomicAdd(&hr->done, min((uint32_t)BS, total - unit * BS));
+        }
+    }
+}
+
+// kHelp: the instantiation with helping (one-word masks only).  Kept apart
+// because its extra state costs the plain traversal registers.
+template <int NW, int BS, bool kHelp>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fused_bpt_kernel(FusedArgs a) {
     __shared__ FusedShared<NW, BS> s;
     constexpr uint32_t kSortCap = sort_cap(BS);
@@ -504,9 +715,14 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
     const uint32_t slot = blockIdx.x;
     constexpr uint32_t C = 64u * NW;
     BatchCtx<NW> b = slot_ctx<NW>(a, slot);
+    HelpRec* const hr = (kHelp && NW == 1 && a.ws.help) ? a.ws.help + slot : nullptr;
 
     if (tid < kNumStats) s.stats[tid] = 0;
-    unsigned long long th_philox = 0, th_live = 0;
+    if (tid == 0) {
+        s.tail = 0;
+        s.probes = 0;
+    }
+    uint32_t th_philox = 0, th_live = 0;  // moved into s.stats before they could overflow
 
     for (;;) {
         __syncthreads();
@@ -528,24 +744,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         __syncthreads();
         if (s.batch >= a.n_batches) break;
         // the batch's job, in scalar registers
-        const FusedJob* jp = a.jobs ? a.jobs + uni32(s.job) : nullptr;
-        DevGraph g;
-        g.rowptr = uni_ptr(jp ? jp->g.rowptr : a.job0.g.rowptr);
-        g.col = uni_ptr(jp ? jp->g.col : a.job0.g.col);
-        g.thr_row = uni_ptr(jp ? jp->g.thr_row : a.job0.g.thr_row);
-        g.thr_edge = uni_ptr(jp ? jp->g.thr_edge : a.job0.g.thr_edge);
-        g.thr_uniform = uni32(jp ? jp->g.thr_uniform : a.job0.g.thr_uniform);
-        g.prob_layout = uni32(jp ? jp->g.prob_layout : a.job0.g.prob_layout);
-        g.n = uni32(jp ? jp->g.n : a.job0.g.n);
-        g.m = uni32(jp ? jp->g.m : a.job0.g.m);
-        const uint64_t seed = uni64(jp ? jp->seed : a.job0.seed);
-        const uint64_t first = uni64(jp ? jp->first_sample : a.job0.first_sample);
-        const uint64_t n_samples = uni64(jp ? jp->n_samples : a.job0.n_samples);
-        const uint64_t out_base = uni64(jp ? jp->out_base : a.job0.out_base);
-        const uint32_t colors = uni32(jp ? jp->colors : a.job0.colors);
-        const uint32_t* order = uni_ptr(jp ? jp->order : a.job0.order);
+        const BatchJob jb = batch_job(a, s.job, s.batch);
+        const DevGraph& g = jb.g;
+        const uint64_t seed = jb.seed;
+        const uint64_t first = jb.first;
+        const uint64_t n_samples = jb.n_samples;
+        const uint64_t out_base = jb.out_base;
+        const uint32_t colors = jb.colors;
+        const uint32_t* order = jb.order;
         const bool ordered = order != nullptr;
-        const uint64_t batch = uni64(s.batch) - uni64(jp ? jp->batch_begin : a.job0.batch_begin);
+        const uint64_t batch = jb.batch;
         const uint32_t n = g.n;
         const uint32_t layout = g.prob_layout;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -576,15 +784,26 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         __syncthreads();
 
         // Frontier initialisation: colour c starts at its sample's start vertex.
+        const Ctr ct_own{s.qlen, &s.tlen, s.cnt};
         for (uint32_t c = tid; c < ncol; c += BS)
-            discover<NW, BS>(b, s, start_of(ordered ? first + s.cidx[c] : s0 + c, n, k0, k1), c, 0, 0, base_tag,
-                             base_tag);
+            discover<NW, false>(b, ct_own, start_of(ordered ? first + s.cidx[c] : s0 + c, n, k0, k1), c, 0, 0,
+                                base_tag, base_tag);
+
+        // Helping: once the launch has no batch left, a heavy chunk of this batch is
+        // published and idle workgroups expand units of it (counters in `hr`).
+        const bool help_ok = kHelp && hr != nullptr && !ordered;
+        bool shared = false;
+        uint32_t hseq = 0;
 
         // Level-synchronous fused traversal.
         uint32_t level = 0, scan_buf = 0;
         for (;;) {
             __syncthreads();  // every discovery of the previous level is done
             const uint32_t qcur = level % 3, qnext = (level + 1) % 3;
+            if (shared) {  // helpers' discoveries are counted in the help record
+                if (tid == 0) s.qlen[qcur] = load_coherent32(&hr->qlen[qcur]);
+                __syncthreads();
+            }
             const uint32_t F = min(s.qlen[qcur], n);
             if (F == 0) break;
             if (level > n) {
@@ -592,7 +811,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                 break;
             }
             if (tid == 0) {
-                s.qlen[(level + 2) % 3] = 0;  // used next by level L+1's discoveries
+                if (shared) store_coherent(&hr->qlen[(level + 2) % 3], 0u);
+                else s.qlen[(level + 2) % 3] = 0;  // used next by level L+1's discoveries
             }
             const int cur = level & 1, nxt = cur ^ 1;
             const uint32_t tag = base_tag + level + 1;
@@ -612,7 +832,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
 #pragma unroll
                 for (uint32_t j = 0; j < kEPT; ++j) {
                     const uint32_t e = j * BS + tid;
-                    vq[j] = e < cnt ? qcur_arr[c0 + e] : 0u;
+                    vq[j] = e < cnt ? (shared ? min(load_coherent32(&qcur_arr[c0 + e]), n - 1) : qcur_arr[c0 + e]) : 0u;
                 }
                 uint32_t rb[kEPT], re[kEPT], rt[kEPT];
                 unsigned long long mk[kEPT][NW];
@@ -677,26 +897,116 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                 }
                 __syncthreads();
 
+                const bool heavy = help_ok && total >= kHelpMinUnits * BS;
+                if (heavy && !shared) {  // are half the workgroups idle? (asked at every 8th heavy chunk)
+                    if (tid == 0) {
+                        if (!s.tail && (++s.probes & 7u) == 0u &&
+                            2 * (a.n_batches - load_coherent64(&a.ctl->finished)) <= gridDim.x)
+                            s.tail = 1u;
+                        s.go = s.tail;
+                    }
+                    __syncthreads();
+                    if (s.go) {  // open the batch to helpers: counters into the help record
+                        if (tid == 0) __threadfence();  // queue and touched entries so far become device-visible
+                        for (uint32_t c = tid; c < 64u; c += BS) store_coherent(&hr->cnt[c], 0u);  // helpers' counts
+                        if (tid == 0) {
+                            for (int q = 0; q < 3; ++q) store_coherent(&hr->qlen[q], s.qlen[q]);
+                            store_coherent(&hr->tlen, s.tlen);
+                            store_coherent64(&hr->batch, s.batch);
+                            store_coherent(&hr->job, s.job);
+                            store_coherent(&hr->done, 0u);
+                            store_coherent64(&hr->claim, 0ull);
+                        }
+                        wait_own_memory_ops();
+                        __syncthreads();
+                        if (tid == 0) {
+                            store_coherent(&hr->state, 1u);
+                            atomicAdd(&a.ctl->open, 1ull);
+                        }
+                        shared = true;
+                    }
+                }
+
                 // Heavy expansion levels are compute-bound while light ones wait on
                 // memory: give the heavy ones issue priority on their SIMDs.
                 set_wave_priority(total >= 8u * BS ? 3 : (total >= 2u * BS ? 2 : (total >= BS / 2 ? 1 : 0)));
-                for (uint32_t t = tid; t < total; t += BS) {
-                    const uint32_t i = find_entry(s.u.st.scan, npos, t);
-                    const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
-                    const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * kQuadsPerItem;
-                    const uint32_t q_end = min(q_first + kQuadsPerItem, ((end - 1) >> 2) + 1);
-                    unsigned long long mask[NW];
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
-                    expand_item<NW, BS>(g, seed, a.gather_mode, b, s, mask, s0, first, ordered, beg, end,
-                                        s.u.st.thr[i], q_first, q_end, nxt, qnext, tag, base_tag, th_philox,
-                                        th_live);
+                if (shared && heavy) {
+                    // publish the chunk, then claim units of it along with the helpers
+                    uint32_t* stage = a.ws.hstage + (size_t)slot * kHelpStagePos * 6;
+                    for (uint32_t p = tid; p < npos; p += BS) {
+                        store_coherent(stage + p, s.u.st.scan[p]);
+                        store_coherent(stage + kHelpStagePos + p, s.u.st.beg[p]);
+                        store_coherent(stage + 2 * kHelpStagePos + p, s.u.st.end[p]);
+                        store_coherent(stage + 3 * kHelpStagePos + p, s.u.st.thr[p]);
+                        const unsigned long long m = s.u.st.mask[p][0];
+                        store_coherent(stage + 4 * kHelpStagePos + p, (uint32_t)m);
+                        store_coherent(stage + 5 * kHelpStagePos + p, (uint32_t)(m >> 32));
+                    }
+                    if (tid == 0) {
+                        store_coherent(&hr->npos, npos);
+                        store_coherent(&hr->nxt, (uint32_t)nxt);
+                        store_coherent(&hr->qnext, qnext);
+                        store_coherent(&hr->done, 0u);
+                    }
+                    wait_own_memory_ops();
+                    __syncthreads();
+                    ++hseq;
+                    if (tid == 0)
+                        atomicExch(&hr->claim, ((unsigned long long)hseq << 48) | ((unsigned long long)total << 20));
+                    uint32_t mine = 0;
+                    for (;;) {
+                        if (tid == 0) s.unit = claim_unit(atomicAdd(&hr->claim, 1ull));
+                        __syncthreads();
+                        const uint32_t unit = s.unit;
+                        __syncthreads();
+                        if ((unsigned long long)unit * BS >= total) break;
+                        const uint32_t t = unit * BS + tid;
+                        if (t < total)
+                            run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, s0, first, ordered, t, npos,
+                                                   nxt, qnext, tag, base_tag, th_philox, th_live);
+                        mine += min((uint32_t)BS, total - unit * BS);
+                    }
+                    wait_own_memory_ops();
+                    __syncthreads();
+                    if (tid == 0) {  // wait for the units helpers claimed
+                        atomicAdd(&hr->done, mine);
+                        uint32_t spins = 0;
+                        while (load_coherent32(&hr->done) < total) {
+                            if (++spins > kWaitSpins) {
+                                atomicOr(&a.ctl->err, (unsigned)kErrHelpTimeout);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                } else if (shared) {
+                    for (uint32_t t = tid; t < total; t += BS)
+                        run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, s0, first, ordered, t, npos,
+                                               nxt, qnext, tag, base_tag, th_philox, th_live);
+                } else {
+                    for (uint32_t t = tid; t < total; t += BS)
+                        run_item<NW, BS, false>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t, npos,
+                                                nxt, qnext, tag, base_tag, th_philox, th_live);
                 }
                 set_wave_priority(0);
+                if (th_philox >= 0x80000000u || th_live >= 0x80000000u) {
+                    atomicAdd(&s.stats[kStatPhilox], (unsigned long long)th_philox);
+                    atomicAdd(&s.stats[kStatLive], (unsigned long long)th_live);
+                    th_philox = th_live = 0;
+                }
                 if (c0 + kChunk < F) __syncthreads();  // the next chunk reuses the staging area
             }
 
             ++level;
+        }
+
+        if (shared) {  // closed to helpers (none holds work); the counters come back to LDS
+            if (tid == 0) {
+                store_coherent(&hr->state, 0u);
+                atomicSub(&a.ctl->open, 1ull);
+                s.tlen = load_coherent32(&hr->tlen);
+            }
+            for (uint32_t c = tid; c < 64u; c += BS) s.cnt[c] += load_coherent32(&hr->cnt[c]);
         }
 
         // ---- RRR set extraction (Listing 1's final loop) ----
@@ -729,7 +1039,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
             uint32_t P = 64;
             while (P < T) P <<= 1;
             for (uint32_t i = tid; i < P; i += BS)
-                s.u.ex.sorted[i] = i < T ? b.touched[i] : kNone;
+                s.u.ex.sorted[i] = i < T ? (shared ? load_coherent32(&b.touched[i]) : b.touched[i]) : kNone;
             __syncthreads();
             for (uint32_t k = 2; k <= P; k <<= 1) {
                 for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -775,11 +1085,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         __syncthreads();
         write_sets<NW, BS>(a.out.pool, b, s, list, T, write_ok);
         wait_own_memory_ops();  // the slot's resets have been performed before it is reused
+        if (tid == 0) atomicAdd(&a.ctl->finished, 1ull);
+    }
+    if constexpr (kHelp && NW == 1) {
+        if (a.ws.help) help_others<NW, BS>(a, s, th_philox, th_live);
     }
 
     // thread-local counters into the workgroup's totals, then the call's
-    atomicAdd(&s.stats[kStatPhilox], th_philox);
-    atomicAdd(&s.stats[kStatLive], th_live);
+    atomicAdd(&s.stats[kStatPhilox], (unsigned long long)th_philox);
+    atomicAdd(&s.stats[kStatLive], (unsigned long long)th_live);
     __syncthreads();
     if (tid < kNumStats) {
         if (tid == kStatMaxLevels) atomicMax(&a.ctl->stats[tid], s.stats[tid]);
@@ -789,12 +1103,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
 
 }  // namespace
 
-hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStream_t stream) {
+hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, bool help, hipStream_t stream) {
 #define BPT_LAUNCH(NW_, BS_) \
-    hipLaunchKernelGGL((fused_bpt_kernel<NW_, BS_>), dim3(grid), dim3(BS_), 0, stream, a)
+    hipLaunchKernelGGL((fused_bpt_kernel<NW_, BS_, false>), dim3(grid), dim3(BS_), 0, stream, a)
+#define BPT_LAUNCH1(BS_)                                                                                        \
+    if (help && a.ws.help)                                                                                      \
+        hipLaunchKernelGGL((fused_bpt_kernel<1, BS_, true>), dim3(grid), dim3(BS_), 0, stream, a);            \
+    else                                                                                                        \
+        hipLaunchKernelGGL((fused_bpt_kernel<1, BS_, false>), dim3(grid), dim3(BS_), 0, stream, a)
     if (block == 128) {
         switch (nw) {
-            case 1: BPT_LAUNCH(1, 128); break;
+            case 1: BPT_LAUNCH1(128); break;
             case 2: BPT_LAUNCH(2, 128); break;
             case 4: BPT_LAUNCH(4, 128); break;
             case 8: BPT_LAUNCH(8, 128); break;
@@ -803,7 +1122,7 @@ hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStre
         }
     } else if (block == 256) {
         switch (nw) {
-            case 1: BPT_LAUNCH(1, 256); break;
+            case 1: BPT_LAUNCH1(256); break;
             case 2: BPT_LAUNCH(2, 256); break;
             case 4: BPT_LAUNCH(4, 256); break;
             case 8: BPT_LAUNCH(8, 256); break;
@@ -812,20 +1131,21 @@ hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStre
         }
     } else if (block == 512) {
         switch (nw) {
-            case 1: BPT_LAUNCH(1, 512); break;
+            case 1: BPT_LAUNCH1(512); break;
             case 2: BPT_LAUNCH(2, 512); break;
             case 4: BPT_LAUNCH(4, 512); break;
             default: return hipErrorInvalidValue;
         }
     } else if (block == 1024) {
         switch (nw) {
-            case 1: BPT_LAUNCH(1, 1024); break;
+            case 1: BPT_LAUNCH1(1024); break;
             default: return hipErrorInvalidValue;
         }
     } else {
         return hipErrorInvalidValue;
     }
 #undef BPT_LAUNCH
+#undef BPT_LAUNCH1
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ enum ErrorBits : unsigned int {
     kErrQueueOverflow = 2u,  // frontier queue exceeded n entries (cannot happen)
     kErrLevelBound = 4u,     // more than n+1 levels in one batch (cannot happen)
     kErrBadRange = 8u,       // a plan's device-supplied sample range leaves [0, 2^34)
+    kErrHelpTimeout = 16u,   // a helped chunk did not complete within the wait bound (cannot happen)
 };
 
 // Small per-call control block in device memory.
@@ -51,8 +52,33 @@ struct Control {
     unsigned long long work_counter; // next batch / sample to claim
     unsigned int err;                // ErrorBits
     unsigned int pad_;
+    unsigned long long finished;     // batches whose sets are written
+    unsigned long long open;         // batches open to helpers
     unsigned long long stats[kNumStats];
 };
+
+// Help record of one slot (one-word masks only).  Once the launch has no
+// batch left to claim, the owner of a batch still running publishes each
+// heavy chunk's staging, and idle workgroups claim units of BS work items of
+// it.  While helpers may join, the batch's discovery counters live here
+// instead of in the owner's LDS.
+struct HelpRec {
+    unsigned long long claim;  // [63:48] chunk number, [47:20] work items, [19:0] next unit to claim
+    unsigned long long batch;  // launch-wide batch index of the helped batch
+    unsigned int state;        // 1 while helpers may join
+    unsigned int done;         // work items of the current chunk finished
+    unsigned int npos;         // staged positions of the current chunk
+    unsigned int nxt;          // parity of the next level (frontier and queue)
+    unsigned int qnext;        // counter of the next level's queue (level + 1) % 3
+    unsigned int job;          // job index of the batch
+    unsigned int pad_[2];
+    unsigned int qlen[3];      // as the owner's LDS counters
+    unsigned int tlen;
+    unsigned int cnt[64];
+    unsigned int pad2_[48];    // 512 bytes
+};
+static_assert(sizeof(HelpRec) == 512, "help records are 512 bytes");
+constexpr unsigned int kHelpStagePos = 2048;  // staged positions per chunk at most (BS * ept for one-word masks)
 
 // Per-slot state of the fused traversal (one slot per resident workgroup).
 // All arrays are zero between batches except `stamp`, whose values only grow.
@@ -64,6 +90,8 @@ struct FusedSlots {
     uint32_t* touched;             // slots * n
     unsigned long long* tbits;     // slots * words(n)
     uint32_t* slot_tag;            // slots
+    HelpRec* help;                 // slots (one-word masks; else null)
+    uint32_t* hstage;              // slots * kHelpStagePos * 6 words: scan, beg, end, thr, mask lo/hi
     uint32_t slots;
 };
 
@@ -123,7 +151,9 @@ struct UnfusedArgs {
 __host__ __device__ inline size_t bitmap_words(uint32_t n) { return ((size_t)n + 63) / 64; }
 
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, hipStream_t stream);
+// help: with one-word masks, let workgroups without a batch left help the
+// batches still running (worth it when sets are large and levels few).
+hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, bool help, hipStream_t stream);
 hipError_t launch_unfused(const UnfusedArgs& a, int grid, hipStream_t stream);
 // CSR assembly of one job's sets: offsets by a scan of `counts`, then a
 // gather from the pool (skipped when the total exceeds `capacity` or the pool
