@@ -581,7 +581,8 @@ __device__ __forceinline__ BatchJob batch_job(const FusedArgs& a, uint32_t job, 
 // Once no batch is left to claim, a workgroup helps batches still running
 // (one-word masks): it joins an open one (the first after its own slot),
 // claims units of the chunks its owner publishes and expands them as the owner
-// would, with the batch's counters in the help record.  It leaves when the
+// would, with the chunk's queue and touched counters in the help record and
+// its per-colour counts in its own LDS (added to the record per unit).  It leaves when the
 // batch closes and stops when every batch is finished; owners never wait for
 // a helper that has not claimed work, so a helper may also give up at any
 // time between claims.
@@ -789,8 +790,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
             discover<NW, false>(b, ct_own, start_of(ordered ? first + s.cidx[c] : s0 + c, n, k0, k1), c, 0, 0,
                                 base_tag, base_tag);
 
-        // Helping: once the launch has no batch left, a heavy chunk of this batch is
-        // published and idle workgroups expand units of it (counters in `hr`).
+        // Helping: once half the workgroups have no batch left, a heavy chunk of this
+        // batch is published and idle workgroups expand units of it.  An open batch
+        // writes queue and touched entries coherently; its queue and touched
+        // counters move to `hr` for the duration of each published chunk.
         const bool help_ok = kHelp && hr != nullptr && !ordered;
         bool shared = false;
         uint32_t hseq = 0;
@@ -800,20 +803,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         for (;;) {
             __syncthreads();  // every discovery of the previous level is done
             const uint32_t qcur = level % 3, qnext = (level + 1) % 3;
-            if (shared) {  // helpers' discoveries are counted in the help record
-                if (tid == 0) s.qlen[qcur] = load_coherent32(&hr->qlen[qcur]);
-                __syncthreads();
-            }
             const uint32_t F = min(s.qlen[qcur], n);
             if (F == 0) break;
             if (level > n) {
                 if (tid == 0) atomicOr(&a.ctl->err, (unsigned)kErrLevelBound);
                 break;
             }
-            if (tid == 0) {
-                if (shared) store_coherent(&hr->qlen[(level + 2) % 3], 0u);
-                else s.qlen[(level + 2) % 3] = 0;  // used next by level L+1's discoveries
-            }
+            if (tid == 0) s.qlen[(level + 2) % 3] = 0;  // used next by level L+1's discoveries
             const int cur = level & 1, nxt = cur ^ 1;
             const uint32_t tag = base_tag + level + 1;
             const uint32_t* qcur_arr = cur ? b.queue1 : b.queue0;
@@ -906,12 +902,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                         s.go = s.tail;
                     }
                     __syncthreads();
-                    if (s.go) {  // open the batch to helpers: counters into the help record
+                    if (s.go) {  // open the batch to helpers
                         if (tid == 0) __threadfence();  // queue and touched entries so far become device-visible
                         for (uint32_t c = tid; c < 64u; c += BS) store_coherent(&hr->cnt[c], 0u);  // helpers' counts
                         if (tid == 0) {
-                            for (int q = 0; q < 3; ++q) store_coherent(&hr->qlen[q], s.qlen[q]);
-                            store_coherent(&hr->tlen, s.tlen);
                             store_coherent64(&hr->batch, s.batch);
                             store_coherent(&hr->job, s.job);
                             store_coherent(&hr->done, 0u);
@@ -942,7 +936,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                         store_coherent(stage + 4 * kHelpStagePos + p, (uint32_t)m);
                         store_coherent(stage + 5 * kHelpStagePos + p, (uint32_t)(m >> 32));
                     }
-                    if (tid == 0) {
+                    if (tid == 0) {  // the queue and touched counters move to the record for this chunk
+                        store_coherent(&hr->qlen[qnext], s.qlen[qnext]);
+                        store_coherent(&hr->tlen, s.tlen);
                         store_coherent(&hr->npos, npos);
                         store_coherent(&hr->nxt, (uint32_t)nxt);
                         store_coherent(&hr->qnext, qnext);
@@ -962,8 +958,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                         if ((unsigned long long)unit * BS >= total) break;
                         const uint32_t t = unit * BS + tid;
                         if (t < total)
-                            run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, s0, first, ordered, t, npos,
-                                                   nxt, qnext, tag, base_tag, th_philox, th_live);
+                            run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, s0,
+                                                   first, ordered, t, npos, nxt, qnext, tag, base_tag, th_philox,
+                                                   th_live);
                         mine += min((uint32_t)BS, total - unit * BS);
                     }
                     wait_own_memory_ops();
@@ -978,11 +975,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                             }
                             __builtin_amdgcn_s_sleep(1);
                         }
+                        s.qlen[qnext] = load_coherent32(&hr->qlen[qnext]);  // back to LDS
+                        s.tlen = load_coherent32(&hr->tlen);
                     }
-                } else if (shared) {
+                } else if (shared) {  // alone, counters in LDS, entries written coherently
                     for (uint32_t t = tid; t < total; t += BS)
-                        run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, s0, first, ordered, t, npos,
-                                               nxt, qnext, tag, base_tag, th_philox, th_live);
+                        run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t, npos, nxt,
+                                               qnext, tag, base_tag, th_philox, th_live);
                 } else {
                     for (uint32_t t = tid; t < total; t += BS)
                         run_item<NW, BS, false>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t, npos,
@@ -1000,11 +999,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
             ++level;
         }
 
-        if (shared) {  // closed to helpers (none holds work); the counters come back to LDS
+        if (shared) {  // closed to helpers (none holds work); their colour counts join ours
             if (tid == 0) {
                 store_coherent(&hr->state, 0u);
                 atomicSub(&a.ctl->open, 1ull);
-                s.tlen = load_coherent32(&hr->tlen);
             }
             for (uint32_t c = tid; c < 64u; c += BS) s.cnt[c] += load_coherent32(&hr->cnt[c]);
         }
