@@ -47,7 +47,18 @@ constexpr int ept(int nw, int bs) {
     return nw == 1 ? (bs <= 512 ? 4 : 2) : (nw == 2 ? (bs <= 256 ? 4 : 2) : (nw == 4 && bs <= 256 ? 2 : 1));
 }
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kQuadsPerItem = 8;  // 4-edge quads one work item covers (one entry lookup)
+constexpr uint32_t kQuadsPerItem = 8;  // 4-edge quads one work item covers at most (one entry lookup)
+
+// 4-edge quads per work item of an entry with pc colours: kQuadsPerItem in
+// general, 4 for entries expected to gather several live colours per edge
+// (the test of expand_item), whose quads are heavy: a finer split keeps more
+// lanes busy there, a coarser one saves entry lookups elsewhere.
+__device__ __forceinline__ uint32_t item_quads(uint32_t pc, uint32_t thr, bool per_edge, uint32_t gather_mode) {
+    const uint32_t p_est = per_edge ? 0x80000000u : thr;
+    const bool gathers = gather_mode == kGatherAlways ||
+                         (gather_mode == kGatherAuto && pc >= 2 && (unsigned long long)pc * p_est >= 0x80000000ull);
+    return gathers ? 4u : kQuadsPerItem;
+}
 
 template <int NW, int BS>
 struct Stage {  // traversal staging of one chunk of ept(NW, BS) * BS frontier entries
@@ -442,11 +453,16 @@ __device__ __forceinline__ void run_item(const DevGraph& g, uint64_t seed, uint3
                                          uint32_t& th_philox, uint32_t& th_live) {
     const uint32_t i = find_entry(s.u.st.scan, npos, t);
     const uint32_t beg = s.u.st.beg[i], end = s.u.st.end[i];
-    const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * kQuadsPerItem;
-    const uint32_t q_end = min(q_first + kQuadsPerItem, ((end - 1) >> 2) + 1);
     unsigned long long mask[NW];
+    uint32_t pc = 0;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) mask[k] = s.u.st.mask[i][k];
+    for (int k = 0; k < NW; ++k) {
+        mask[k] = s.u.st.mask[i][k];
+        pc += (uint32_t)__popcll(mask[k]);
+    }
+    const uint32_t qpi = item_quads(pc, s.u.st.thr[i], g.prob_layout == BPT_PROB_EDGE, gather_mode);
+    const uint32_t q_first = (beg >> 2) + (t - s.u.st.scan[i]) * qpi;
+    const uint32_t q_end = min(q_first + qpi, ((end - 1) >> 2) + 1);
     expand_item<NW, BS, kSh>(g, seed, gather_mode, b, s, ct, mask, s0, first, ordered, beg, end, s.u.st.thr[i],
                              q_first, q_end, nxt, qnext, tag, base_tag, th_philox, th_live);
 }
@@ -860,7 +876,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     const bool never = (layout != BPT_PROB_EDGE) && rt[j] == 0;
                     const uint32_t quads =
                         (!ok || deg == 0 || never || pc == 0) ? 0u : ((end - 1) >> 2) - (beg >> 2) + 1;
-                    my_items[j] = (quads + kQuadsPerItem - 1) / kQuadsPerItem;
+                    my_items[j] = item_quads(pc, rt[j], layout == BPT_PROB_EDGE, a.gather_mode) == 4u
+                                      ? (quads + 3) >> 2
+                                      : (quads + kQuadsPerItem - 1) / kQuadsPerItem;
                     items += my_items[j];
                     s.u.st.beg[pos] = beg;
                     s.u.st.end[pos] = end;
