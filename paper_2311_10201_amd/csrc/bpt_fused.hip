@@ -11,8 +11,9 @@
 //   expansion        every in-edge e = (u -> v) of the entry is tried for
 //                    every colour of the mask.  Work items are (entry, up to
 //                    eight 4-edge quads) spread evenly over the workgroup's
-//                    lanes; each evaluates one Philox block per colour and
-//                    quad, i.e. the coins of four consecutive in-edges.
+//                    lanes (four quads per item where colours are gathered);
+//                    each evaluates one Philox block per colour and quad,
+//                    i.e. the coins of four consecutive in-edges.
 //                    Coins are flipped before any neighbour data is read
 //                    ("flip before gather"): `col[e]` and visited[u] are only
 //                    touched for live coins.
@@ -28,6 +29,11 @@
 // touched-vertex bitmap otherwise), each colour's members are ranked with
 // wavefront ballots, written to the output pool in ascending order, and the
 // slot's state is reset through the same list.
+//
+// A second instantiation (kHelp, one-word masks) adds helping at the end of a
+// launch: once half the workgroups have no batch left, an owner publishes each
+// heavy chunk of its batch to device memory and idle workgroups expand units of
+// its work items (help_others).  The host picks it for graphs with large sets.
 #include "bpt.h"
 #include "bpt_internal.hpp"
 #include "bpt_rng.hpp"
