@@ -833,9 +833,13 @@ def main() -> int:
 
     achieved = blocks / trav_s
     traffic = measured_traffic(args.workload, colors, cnt.workgroup_size)
+    # the library's rule for the instantiation with tail helping (one-word masks,
+    # sets of 1,024+ members on average, unless BPT_HELP forces it)
+    forced = os.environ.get("BPT_HELP")
+    helping = colors <= 64 and (forced == "1" if forced in ("0", "1") else cnt.members >= 1024 * S)
     roofline = {
         "bound": "alu",
-        "kernel": f"fused_bpt_kernel<{colors // 64}, {cnt.workgroup_size}>",
+        "kernel": f"fused_bpt_kernel<{max(1, colors // 64)}, {cnt.workgroup_size}, {'true' if helping else 'false'}>",
         "achieved": achieved / 1e9,
         "peak": PEAK_PHILOX_BLOCKS / 1e9,
         "unit": "G Philox4x32-10 blocks/s",
