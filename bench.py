@@ -1,14 +1,17 @@
 #!/usr/bin/env python3
 """RRR-set sampling throughput on one MI355X: fused BPTs vs the unfused traversal.
 
-    python bench.py [--steps K] [--warmup W] [--workload rmat20-wc] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--workload rmat22-p0.01] [--gpus 1]
 
 One "step" samples the whole workload once (all its RRR sets) with the fused
 traversal at the chosen colour count; inputs are resident in HBM and the sets
-are written to device memory.  Prints one JSON line: samples/s (the value),
-traversed edges/s, the unfused and other colour-count rates on the same GPU,
+are written to device memory.  The default workload is the largest one that
+fits one GPU: R-MAT scale 22, uniform p = 0.01, 1,000,000 samples.  Prints one
+JSON line: samples/s (the value), traversed edges/s, the unfused and other
+colour-count rates on the same GPU (timed with --variant-steps steps each),
 the traversal kernel's roofline, and the CPU oracle timed on the host cores
-(whose output is also compared with the GPU's, set by set).
+on a fixed subset of sample ids (whose sets are also compared with the GPU's,
+set by set).
 """
 
 from __future__ import annotations
@@ -28,10 +31,11 @@ METRIC = ("RRR samples/sec and traversed edges/sec (fused vs unfused, bit-exact)
 WORKLOADS = {
     # R-MAT scale 20, edge factor 16, weighted cascade, 100,000 samples
     "rmat20-wc": dict(kind="rmat", scale=20, ef=16, a=0.57, b=0.19, c=0.19, graph_seed=20, prob="wc",
-                      samples=100_000, seed=42, colors=(64, 256), cpu_stride=1),
+                      samples=100_000, seed=42, colors=(64, 256), cpu_stride=1, listing_stride=1),
     # R-MAT scale 22, edge factor 16, uniform p = 0.01, 1,000,000 samples
+    # (the CPU oracle runs on the sample ids that are multiples of 97: 10,310 sets)
     "rmat22-p0.01": dict(kind="rmat", scale=22, ef=16, a=0.57, b=0.19, c=0.19, graph_seed=22, prob=0.01,
-                         samples=1_000_000, seed=42, colors=(64, 256), cpu_stride=401),
+                         samples=1_000_000, seed=42, colors=(64, 128, 256), cpu_stride=97, listing_stride=20),
     # 32 uneven R-MAT instances (scale 12-21, edge factor 8/16/32, uniform p 0.01/0.05/0.1 or weighted
     # cascade, 1k-200k samples, log-uniform), all sampled by one bpt_sample_rrr_jobs call; each
     # instance's sample count is capped so its sets hold at most 2^27 vertex ids
@@ -45,7 +49,7 @@ WORKLOADS = {
                    check_every=100),
     # Erdos-Renyi n = 1,000, m = 10,000, p = 0.1, 64 samples
     "er1000-p0.1": dict(kind="er", n=1000, m=10_000, graph_seed=42, prob=0.1, samples=64, seed=42, colors=(64,),
-                        cpu_stride=1),
+                        cpu_stride=1, listing_stride=1),
 }
 
 # ALU roofline of one Philox4x32-10 block on gfx950: per round two
@@ -659,7 +663,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20-wc", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat22-p0.01", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant-steps", type=int, default=2,
+                    help="timed steps of each comparison variant (unfused, other colour counts)")
     ap.add_argument("--colors", type=int, default=0, help="0: pick the fastest listed colour count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -766,24 +772,24 @@ def main() -> int:
         if not variants:
             print(f"unknown variant {args.only}", file=sys.stderr)
             return 2
+    # one untimed call per variant (it also builds the variant's workspace);
+    # the fastest listed colour count becomes the headline unless --colors names one
     warm = {}
     for c, fl in variants:
         name = "unfused" if fl else f"fused{c}"
         between_variants()
-        for i in range(max(1, args.warmup)):
-            warm[name], cnt = timed_one(c, fl)
-            total = cnt.members
-        log(f"warmup {name}: {warm[name] * 1e3:.2f} ms, members={total}")
+        warm[name], cnt = timed_one(c, fl)
+        log(f"first call {name}: {warm[name] * 1e3:.2f} ms, members={cnt.members}")
 
     fused_done = [c for c in w["colors"] if f"fused{c}" in warm]
     if not fused_done:
         print("--only must name a fused variant (the headline is the fused traversal)", file=sys.stderr)
         return 2
     colors = args.colors or min(fused_done, key=lambda c: warm[f"fused{c}"])
-    log(f"timing fused C={colors}: {args.steps} steps")
     between_variants()
-    if big:
-        step(colors)  # re-create the workspace outside the timed steps
+    for _ in range(max(1, args.warmup)):
+        timed_one(colors, 0)
+    log(f"timing fused C={colors}: {args.steps} steps after {max(1, args.warmup)} warmup calls")
     sec, cnts = timed(colors, 0, args.steps)
     cnt = cnts[-1]
     value = S / sec
@@ -798,23 +804,29 @@ def main() -> int:
     if w["cpu_stride"] == 1:
         gpu_sets = vert[:total].cpu().numpy().view(np.uint32).copy()
     else:
-        gpu_sets = np.concatenate([vert[int(gpu_off[i]):int(gpu_off[i + 1])].cpu().numpy().view(np.uint32)
-                                   for i in check_ids.tolist()])
+        idx = torch.as_tensor(check_ids.astype(np.int64), device="cuda")
+        lo, hi = off[idx], off[idx + 1]
+        lens = hi - lo
+        pos = torch.repeat_interleave(lo - (torch.cumsum(lens, 0) - lens), lens)
+        pos += torch.arange(int(lens.sum().item()), device="cuda")
+        gpu_sets = vert[pos].cpu().numpy().view(np.uint32).copy()
+        del idx, lo, hi, lens, pos
 
     others = {}
     for c, fl in variants:
         name = "unfused" if fl else f"fused{c}"
         if not fl and c == colors:
-            others[name] = dict(samples_per_s=value, ms_per_step=sec * 1e3,
-                                traversal_ms=trav_s * 1e3, edge_accesses=cnt.edge_accesses)
+            others[name] = dict(samples_per_s=value, ms_per_step=sec * 1e3, steps=args.steps,
+                                traversal_ms=trav_s * 1e3, edge_accesses=cnt.edge_accesses,
+                                workgroups=cnt.workgroups)
             continue
         between_variants()
         if big:
-            step(c, fl)
-        s2, c2 = timed(c, fl, args.steps)
-        others[name] = dict(samples_per_s=S / s2, ms_per_step=s2 * 1e3,
+            step(c, fl)  # re-create the workspace outside the timed steps
+        s2, c2 = timed(c, fl, max(1, args.variant_steps))
+        others[name] = dict(samples_per_s=S / s2, ms_per_step=s2 * 1e3, steps=max(1, args.variant_steps),
                             traversal_ms=sum(x.traversal_ns for x in c2) / len(c2) / 1e6,
-                            edge_accesses=c2[-1].edge_accesses)
+                            edge_accesses=c2[-1].edge_accesses, workgroups=c2[-1].workgroups)
         log(f"{name}: {s2 * 1e3:.2f} ms/step")
 
     # host-resident result (adds the device-to-host copy of the CSR over PCIe);
@@ -890,7 +902,17 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         import oracle
-        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        from concurrent.futures import ThreadPoolExecutor
+        affinity = len(os.sched_getaffinity(0))
+        # the host's CPU share per GPU is 16 cores; use every core of it the process may run on
+        threads = args.cpu_threads or min(16, affinity)
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
+        log(f"host: nproc {os.cpu_count()}, affinity {affinity} cores, {cpu_model}; oracle on {threads} threads")
         og = oracle.Graph(n, src, dst, prob)
         t = time.perf_counter()
         ref = og.sample_ids(seed, check_ids, nthreads=threads)
@@ -898,22 +920,51 @@ def main() -> int:
         sizes = (gpu_off[check_ids.astype(np.int64) + 1] - gpu_off[check_ids.astype(np.int64)]).astype(np.uint64)
         same = bool(np.array_equal(np.diff(ref.offsets), sizes) and np.array_equal(ref.members, gpu_sets))
         n_cpu = len(check_ids)
-        cpu_model = ""
-        try:
-            with open("/proc/cpuinfo") as f:
-                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-        except OSError:
-            pass
         result["cpu_baseline"] = {
             "value": n_cpu / cpu_s, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": (f"all {S} samples of the workload" if n_cpu == S else
-                       f"{n_cpu} of the {S} samples (every {w['cpu_stride']}th id)") +
+                       f"{n_cpu} of the {S} samples (the ids that are multiples of {w['cpu_stride']})") +
                       f", one reverse BFS per sample, {cpu_model}",
             "edges_per_s": float(ref.te.sum()) / cpu_s,
+            "seconds": cpu_s,
+            "host": {"nproc": os.cpu_count(), "affinity_cores": affinity, "cpu_model": cpu_model},
         }
         result["parity"] = (f"bit-exact vs oracle on {n_cpu} of {S} sets" if same else "MISMATCH vs oracle")
         log(f"cpu oracle: {cpu_s:.2f}s on {threads} threads; parity {'ok' if same else 'FAILED'}")
         if not same:
+            print(json.dumps(result), flush=True)
+            return 1
+        # Philox blocks Listing 1 would still need (its visited mask skips the coins
+        # of sources already reached at the member's depth or less), as a share of
+        # the blocks this kernel evaluates, from the oracle's sets of a subset of ids
+        sub = np.arange(0, len(ref), w["listing_stride"])
+        lens = (ref.offsets[sub + 1] - ref.offsets[sub]).astype(np.int64)
+        pos = np.repeat(ref.offsets[sub].astype(np.int64) - (np.cumsum(lens) - lens), lens) + np.arange(lens.sum())
+        part_off = np.zeros(len(sub) + 1, np.uint64)
+        part_off[1:] = np.cumsum(lens)
+        part_mem, part_dist = ref.members[pos], ref.dist[pos]
+        chunks = [c for c in np.array_split(np.arange(len(sub)), threads) if len(c)]
+
+        def blocks_of(ch):
+            lo, hi = int(part_off[ch[0]]), int(part_off[ch[-1] + 1])
+            piece = oracle.RRRSets(ref.sample_ids[sub[ch]], part_off[ch[0]:ch[-1] + 2] - part_off[ch[0]],
+                                   part_mem[lo:hi], part_dist[lo:hi], ref.te[sub[ch]])
+            a, l = oracle.coin_blocks(og, piece)
+            return int(a.sum()), int(l.sum())
+
+        with ThreadPoolExecutor(threads) as ex:
+            sums = list(ex.map(blocks_of, chunks))
+        b_all, b_listing = sum(x[0] for x in sums), sum(x[1] for x in sums)
+        ratio = b_listing / max(1, b_all)
+        roofline["listing_blocks_ratio"] = ratio
+        roofline["frac_of_listing_coins"] = roofline["frac"] * ratio
+        roofline["listing_note"] = (f"Philox blocks Listing 1's visited mask leaves needed / blocks evaluated = "
+                                    f"{b_listing}/{b_all} on the oracle's sets of {len(sub)} sample ids "
+                                    f"(multiples of {w['cpu_stride'] * w['listing_stride']}); frac_of_listing_coins "
+                                    "counts only those blocks as useful work")
+        if w["cpu_stride"] * w["listing_stride"] == 1 and b_all != blocks:
+            log(f"Philox blocks: kernel {blocks}, oracle {b_all}")
+            result["parity"] = "MISMATCH: Philox-block counter differs from the oracle's count"
             print(json.dumps(result), flush=True)
             return 1
 

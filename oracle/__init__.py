@@ -80,6 +80,8 @@ def _load():
     lib.or_result_total.restype = u64
     lib.or_result_export.argtypes = [vp, vp, vp, vp, vp]
     lib.or_result_export.restype = None
+    lib.or_quad_accounting.argtypes = [vp, u64, vp, vp, vp, i32, vp, vp, vp]
+    lib.or_quad_accounting.restype = None
     _lib = lib
     return lib
 
@@ -242,6 +244,62 @@ def fused_edge_accesses(graph: Graph, sets: RRRSets, colors: int, order: np.ndar
         verts = (pairs >> np.uint64(32)).astype(np.int64)
         total += int(indeg[verts].sum())
     return total
+
+
+def _rows_one_threshold(graph: Graph) -> bool:
+    """True when every in-edge of a vertex has the same threshold (a uniform
+    probability, or one that depends only on the destination as in weighted
+    cascade): then one stored threshold per row tells whether any of its
+    coins can be live."""
+    b, _, thr = graph.incoming()
+    if graph.m < 2:
+        return True
+    row = np.repeat(np.arange(graph.n, dtype=np.int64), np.diff(b).astype(np.int64))
+    return bool(np.all((thr[1:] == thr[:-1]) | (row[1:] != row[:-1])))
+
+
+def coin_blocks(graph: Graph, sets: RRRSets) -> tuple[np.ndarray, np.ndarray]:
+    """Per-set Philox block counts under the keyed coin layout: coin (s, e)
+    is word e & 3 of one block keyed on (e >> 2, s), so a block serves the
+    four edges of a "quad" 4q .. 4q+3 of one sample.
+
+    Returns (all, listing), uint64 per set:
+      all      quads met by the rows of the set's members: the blocks a
+               traversal evaluates when it draws the coins of every in-edge of
+               each expanded (vertex, sample) before looking at the source
+               (rows that can never be live are skipped when each row has one
+               threshold, and rows without in-edges have no quad);
+      listing  of those, the quads holding an edge u -> v whose source u is
+               not in the set at a depth <= depth(v): the only coins Listing 1
+               can need, since it masks each edge's colours with
+               ~visited[u] and such a source is visited before v's level is
+               expanded.
+    """
+    count = len(sets)
+    all_ = np.zeros(max(count, 1), dtype=np.uint64)
+    listing = np.zeros(max(count, 1), dtype=np.uint64)
+    if count:
+        dist = np.full(graph.n, -1, dtype=np.int32)
+        members = np.ascontiguousarray(sets.members, dtype=np.uint32)
+        mdist = np.ascontiguousarray(sets.dist, dtype=np.int32)
+        offsets = np.ascontiguousarray(sets.offsets, dtype=np.uint64)
+        _load().or_quad_accounting(graph._h, count, _ptr(offsets), _ptr(members) if len(members) else None,
+                                   _ptr(mdist) if len(mdist) else None, int(_rows_one_threshold(graph)),
+                                   _ptr(dist), _ptr(all_), _ptr(listing))
+    return all_[:count], listing[:count]
+
+
+def philox_blocks(graph: Graph, sets: RRRSets) -> int:
+    """Total Philox blocks of a flip-before-gather traversal of ``sets`` (the
+    ``all`` column of :func:`coin_blocks`).  Fusing does not change it: every
+    (member, sample) pair draws its own coins."""
+    return int(coin_blocks(graph, sets)[0].sum())
+
+
+def listing_blocks(graph: Graph, sets: RRRSets) -> int:
+    """Total Philox blocks Listing 1's visited mask leaves needed (the
+    ``listing`` column of :func:`coin_blocks`)."""
+    return int(coin_blocks(graph, sets)[1].sum())
 
 
 def sorted_start_order(sets: RRRSets, rank: np.ndarray | None = None) -> np.ndarray:

@@ -445,6 +445,65 @@ or_result* or_sample_ids(const or_graph* g, uint64_t seed, const uint64_t* ids, 
     return r;
 }
 
+/* ------------------------------------------------------------------ */
+/* Coin-block accounting of a result.  Under the coin layout above one */
+/* Philox block yields the coins of the four edges 4q .. 4q+3 ("quad"  */
+/* q) of one sample, so expanding member v of sample s for all of v's  */
+/* in-edges evaluates one block per quad that v's row meets.           */
+/* ------------------------------------------------------------------ */
+/* For every set i of a result (count sets in CSR form: offsets, members
+ * ascending, member_dist their BFS depths, as or_result_export writes them)
+ * and every member v with in-edges:
+ *   all[i]     += quads met by v's row [in_begin[v], in_begin[v+1]), unless
+ *                 skip_dead and every threshold of the row is 0 (a row whose
+ *                 coins can never be live, known from one stored threshold);
+ *   listing[i] += quads met by v's row that hold an edge u -> v whose source
+ *                 u is not a member at depth <= depth(v).  Listing 1 masks the
+ *                 colours of an edge with ~visited[u]; a source at depth <=
+ *                 depth(v) has been visited before v's level is expanded in
+ *                 any level-synchronous order, so only the other edges need a
+ *                 coin.  (A row counted in `listing` always counts in `all`.)
+ * dist is scratch of n entries that must hold -1 everywhere on entry; it is
+ * left so. */
+void or_quad_accounting(const or_graph* g, uint64_t count, const uint64_t* offsets, const uint32_t* members,
+                        const int32_t* member_dist, int skip_dead, int32_t* dist, uint64_t* all, uint64_t* listing)
+{
+    for (uint64_t i = 0; i < count; ++i) {
+        uint64_t lo = offsets[i], hi = offsets[i + 1];
+        uint64_t a = 0, l = 0;
+        for (uint64_t j = lo; j < hi; ++j)
+            dist[members[j]] = member_dist[j];
+        for (uint64_t j = lo; j < hi; ++j) {
+            uint32_t v = members[j];
+            uint64_t b = g->in_begin[v], e = g->in_begin[v + 1];
+            if (b == e)
+                continue;
+            if (skip_dead) {
+                int dead = 1;
+                for (uint64_t x = b; x < e; ++x)
+                    dead = dead && g->in_thr[x] == 0;
+                if (dead)
+                    continue;
+            }
+            for (uint64_t q = b >> 2; q <= (e - 1) >> 2; ++q) {
+                a += 1;
+                uint64_t x0 = q << 2 < b ? b : q << 2;
+                uint64_t x1 = (q << 2) + 4 > e ? e : (q << 2) + 4;
+                int need = 0;
+                for (uint64_t x = x0; x < x1; ++x) {
+                    int32_t du = dist[g->in_src[x]];
+                    need = need || du < 0 || du > member_dist[j];
+                }
+                l += need ? 1 : 0;
+            }
+        }
+        for (uint64_t j = lo; j < hi; ++j)
+            dist[members[j]] = -1;
+        all[i] = a;
+        listing[i] = l;
+    }
+}
+
 uint64_t or_result_count(const or_result* r) { return r->count; }
 uint64_t or_result_total(const or_result* r) { return r->offsets[r->count]; }
 void or_result_export(const or_result* r, uint64_t* offsets, uint32_t* members, int32_t* dist,

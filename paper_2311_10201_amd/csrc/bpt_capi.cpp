@@ -93,9 +93,11 @@ struct Workspace {
     void* order_scratch = nullptr;  // sorted starts: keys, indices and sort temporaries
     size_t order_bytes = 0;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // traversal start, traversal end, finalize end
-    // When a call ends in BPT_ERANGE its sets stay in counts / where / pool;
-    // the retry with a larger buffer and the same arguments only re-runs the
-    // CSR assembly.  Any other call clears this.
+    // When a bpt_sample_rrr_device call ends in BPT_ERANGE its sets stay in
+    // counts / where / pool; the retry with a larger buffer and the same
+    // arguments only re-runs the CSR assembly.  Every other launch on the
+    // workspace (another sampling call, a multi-job launch, a tuning trial)
+    // clears this before it overwrites those arrays.
     bool have_last = false;
     uint64_t last_first = 0, last_samples = 0, last_seed = 0;
     uint32_t last_colors = 0;
@@ -504,12 +506,14 @@ void release_or_discard(bpt_graph* g, Workspace* ws, const CallResult& r) {
 
 // Runs the traversal and the CSR assembly.  When `own_output` is set the
 // result goes to the workspace's own device buffers (sized to fit).
+// `retry_ok`: the caller is bpt_sample_rrr_device, whose retry after
+// BPT_ERANGE may reuse the sets the failed call left in the workspace.
 int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32_t colors, uint64_t seed,
                  uint32_t flags, hipStream_t stream, unsigned long long* d_offsets, uint32_t* d_vertices,
-                 uint64_t capacity, bool own_output, CallResult* res) {
+                 uint64_t capacity, bool own_output, bool retry_ok, CallResult* res) {
     const bool unfused = (flags & BPT_FLAG_UNFUSED) != 0;
     const bool sorted = (flags & BPT_FLAG_SORTED_STARTS) != 0;
-    const bool reuse = ws->have_last && ws->last_first == first && ws->last_samples == S &&
+    const bool reuse = retry_ok && ws->have_last && ws->last_first == first && ws->last_samples == S &&
                        ws->last_seed == seed && ws->last_colors == colors && ws->last_flags == flags;
     if (reuse) {
         if (own_output) {
@@ -674,6 +678,7 @@ bpt_graph* check_graph(const void* h) {
 int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<uint32_t>& live,
              const std::vector<uint32_t>& colors, hipStream_t stream, bpt_counters* counters) {
     const uint32_t J = (uint32_t)live.size();
+    ws->have_last = false;  // counts, where and pool are overwritten below
     ensure_jobs(ws, J);
     uint64_t n_batches = 0, total_samples = 0;
     for (uint32_t i = 0; i < J; ++i) {
@@ -903,7 +908,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
         CallResult res;
         const int rc = run_sampling(gg, ws, first_sample, n_samples, colors, seed, flags, st,
                                     reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity, false,
-                                    &res);
+                                    true, &res);
         release_or_discard(gg, ws, res);
         ws = nullptr;
         if (rc == BPT_OK || rc == BPT_ERANGE) {
@@ -1165,7 +1170,7 @@ bpt_rrr* bpt_sample_rrr(bpt_graph* g, uint64_t n_samples, uint32_t colors_per_ba
             ws = acquire(gg, mask_words(colors), (n_samples + colors - 1) / colors);
             CallResult res;
             const int rc = run_sampling(gg, ws, 0, n_samples, colors, seed, 0u, nullptr, nullptr, nullptr, 0,
-                                        true, &res);
+                                        true, false, &res);
             if (rc != BPT_OK) {
                 release_or_discard(gg, ws, res);
                 const int keep_status = t_status;
@@ -1417,7 +1422,8 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
             uint64_t ns = ~0ull;
             for (int rep = 0; rep < 2; ++rep) {  // the first run also loads the kernel
                 CallResult res;
-                const int rc = run_sampling(gg, ws, 0, S, c, seed, 0u, nullptr, nullptr, nullptr, 0, true, &res);
+                const int rc = run_sampling(gg, ws, 0, S, c, seed, 0u, nullptr, nullptr, nullptr, 0, true, false,
+                                              &res);
                 if (rc != BPT_OK) {
                     release_or_discard(gg, ws, res);
                     return 0;  // status set by run_sampling

@@ -37,6 +37,7 @@ def test_helping_matches_oracle(heavy, monkeypatch, force, colors):
     assert_same_sets(off, ver, ref, f"BPT_HELP={force} colours {colors}")
     assert cnt.sample_edges == int(ref.te.sum())
     assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, colors)
+    assert cnt.philox_blocks == oracle.philox_blocks(og, ref)  # helpers' blocks included
 
 
 def test_helping_in_a_multi_job_launch(heavy, monkeypatch):

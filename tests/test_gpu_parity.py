@@ -48,6 +48,7 @@ def test_er_all_colors_and_unfused(er_case):
     S = 3000  # ragged: not a multiple of any colour count
     ref = og.sample(42, S, nthreads=8)
     te = int(ref.te.sum())
+    blocks = oracle.philox_blocks(og, ref)
     for c in COLORS:
         announce(f"ER S={S} C={c}")
         off, ver, cnt = sample_device(g, 0, S, c, 42)
@@ -56,11 +57,13 @@ def test_er_all_colors_and_unfused(er_case):
         assert cnt.members == int(ref.offsets[-1])
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
         assert cnt.frontier_entries == oracle.fused_frontier_entries(ref, c)
+        assert cnt.philox_blocks == blocks
         assert cnt.batches == (S + c - 1) // c
     announce(f"ER S={S} unfused")
     off, ver, cnt = sample_device(g, 0, S, 0, 42, flags=bpt.BPT_FLAG_UNFUSED)
     assert_same_sets(off, ver, ref, "unfused")
     assert cnt.edge_accesses == te and cnt.sample_edges == te
+    assert cnt.philox_blocks == blocks
 
 
 @pytest.mark.parametrize("layout", ["uniform", "row", "edge"])
@@ -88,12 +91,15 @@ def test_probability_layouts(layout):
     og = oracle.Graph(n, src, dst, prob)
     S = 2500
     ref = og.sample(7, S, nthreads=8)
+    blocks = oracle.philox_blocks(og, ref)
     for c in (64, 256):
         off, ver, cnt = sample_device(g, 0, S, c, 7)
         assert_same_sets(off, ver, ref, f"{layout} C={c}")
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
-    off, ver, _ = sample_device(g, 0, S, 0, 7, flags=bpt.BPT_FLAG_UNFUSED)
+        assert cnt.philox_blocks == blocks
+    off, ver, cnt = sample_device(g, 0, S, 0, 7, flags=bpt.BPT_FLAG_UNFUSED)
     assert_same_sets(off, ver, ref, f"{layout} unfused")
+    assert cnt.philox_blocks == blocks
 
 
 def test_degenerate_probabilities():
@@ -103,10 +109,15 @@ def test_degenerate_probabilities():
         announce(f"p={p}")
         prob = graphgen.uniform_prob(len(src), p)
         g = bpt.bpt_create_graph(n, src, dst, prob)
-        ref = oracle.Graph(n, src, dst, prob).sample(3, 700, nthreads=8)
+        og = oracle.Graph(n, src, dst, prob)
+        ref = og.sample(3, 700, nthreads=8)
+        blocks = oracle.philox_blocks(og, ref)
+        if p == 0.0:
+            assert blocks == 0  # rows that can never be live draw no coins
         for c, flags in ((64, 0), (1024, 0), (0, bpt.BPT_FLAG_UNFUSED)):
-            off, ver, _ = sample_device(g, 0, 700, c, 3, flags=flags)
+            off, ver, cnt = sample_device(g, 0, 700, c, 3, flags=flags)
             assert_same_sets(off, ver, ref, f"p={p} C={c} flags={flags}")
+            assert cnt.philox_blocks == blocks
         if p == 0.0:
             assert np.all(np.diff(ref.offsets) == 1)
 
@@ -171,6 +182,39 @@ def test_erange_and_repeatability(er_case):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_erange_retry_after_other_launches(er_case):
+    """A retry after BPT_ERANGE returns the oracle's sets even when a
+    multi-job launch and a tuning run used the graph's cached workspaces in
+    between (they overwrite the sets the failed call left there), and the
+    tuning trial is not served from those sets either."""
+    import torch
+    n, src, dst, prob = er_case
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    og = oracle.Graph(n, src, dst, prob)
+    S, seed = 500, 9
+    ref = og.sample(seed, S, nthreads=8)
+    off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    vert = torch.empty(8, dtype=torch.int32, device="cuda")
+    announce("ERANGE, then a jobs call on the same graph")
+    st, total, _ = bpt.bpt_sample_rrr_device(g, 0, S, 64, seed, 0, None, off, vert, 8)
+    assert st == bpt.BPT_ERANGE and total == int(ref.offsets[-1])
+    other = og.sample(3, 700, first_sample=40, nthreads=8)
+    job = bpt.Job(g, 40, 700, 3, torch.empty(701, dtype=torch.int64, device="cuda"),
+                  torch.empty(int(other.offsets[-1]), dtype=torch.int32, device="cuda"), int(other.offsets[-1]), 64)
+    st, _ = bpt.bpt_sample_rrr_jobs([job])
+    assert st == bpt.BPT_OK
+    announce("retry after the jobs call")
+    a = sample_device(g, 0, S, 64, seed)
+    assert_same_sets(a[0], a[1], ref, "retry after a jobs call")
+    assert a[2].traversal_ns > 0
+    announce("ERANGE, then a tuning run")
+    st, _, _ = bpt.bpt_sample_rrr_device(g, 0, S, 64, seed, 0, None, off, vert, 8)
+    assert st == bpt.BPT_ERANGE
+    assert bpt.bpt_tune_colors(g, S, seed) in (8, 16, 32, 64, 128, 256, 512, 1024)
+    a = sample_device(g, 0, S, 64, seed)
+    assert_same_sets(a[0], a[1], ref, "retry after tuning")
+
+
 def test_invalid_sampling_arguments(er_case):
     n, src, dst, prob = er_case
     g = bpt.bpt_create_graph(n, src, dst, prob)
@@ -226,8 +270,8 @@ def test_tuned_colors_are_remembered(er_case):
 
 def hub_graph(n=20_000, hubs=12, hub_in=9_000, hub_out=1_500, m_rand=60_000, seed=17):
     """Random graph plus hub vertices with thousands of in-edges (rows that the
-    fused kernel splits into device-wide tasks) and many out-edges (so samples
-    reach them often)."""
+    fused kernel splits into many work items over a workgroup's lanes) and many
+    out-edges (so samples reach them often)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     src = [rng.integers(0, n, m_rand)]
     dst = [rng.integers(0, n, m_rand)]
@@ -244,7 +288,7 @@ def hub_graph(n=20_000, hubs=12, hub_in=9_000, hub_out=1_500, m_rand=60_000, see
 
 
 @pytest.mark.parametrize("layout", ["uniform", "row", "edge"])
-def test_hub_rows_split_across_workgroups(layout):
+def test_hub_rows_split_into_work_items(layout):
     n, src, dst = hub_graph()
     if layout == "uniform":
         prob = graphgen.uniform_prob(len(src), 0.02)
@@ -260,12 +304,14 @@ def test_hub_rows_split_across_workgroups(layout):
     ref = og.sample(23, S, nthreads=8)
     indeg = og.indegree()
     hub_expansions = int(np.sum(indeg[ref.members.astype(np.int64)] >= 4096))
-    assert hub_expansions > 100  # the split path is exercised
+    assert hub_expansions > 100  # rows of over a thousand 8-quad items are expanded
+    blocks = oracle.philox_blocks(og, ref)
     for c in COLORS:
         off, ver, cnt = sample_device(g, 0, S, c, 23)
         assert_same_sets(off, ver, ref, f"hub {layout} C={c}")
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
         assert cnt.sample_edges == int(ref.te.sum())
+        assert cnt.philox_blocks == blocks
     off, ver, _ = sample_device(g, 0, S, 0, 23, flags=bpt.BPT_FLAG_UNFUSED)
     assert_same_sets(off, ver, ref, f"hub {layout} unfused")
 
@@ -305,6 +351,7 @@ def test_colour_schedules(mode, layout, monkeypatch):
     og = oracle.Graph(n, src, dst, prob)
     S = 1500
     ref = og.sample(37, S, nthreads=8)
+    blocks = oracle.philox_blocks(og, ref)
     monkeypatch.setenv("BPT_GATHER", mode)
     g = bpt.bpt_create_graph(n, src, dst, prob)
     for c in COLORS:
@@ -312,4 +359,5 @@ def test_colour_schedules(mode, layout, monkeypatch):
         off, ver, cnt = sample_device(g, 0, S, c, 37)
         assert_same_sets(off, ver, ref, f"{mode} {layout} C={c}")
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+        assert cnt.philox_blocks == blocks
         assert cnt.live_coins <= cnt.philox_blocks * 4
