@@ -664,7 +664,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22-p0.01", choices=sorted(WORKLOADS))
-    ap.add_argument("--variant-steps", type=int, default=2,
+    ap.add_argument("--variant-steps", type=int, default=1,
                     help="timed steps of each comparison variant (unfused, other colour counts)")
     ap.add_argument("--colors", type=int, default=0, help="0: pick the fastest listed colour count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -772,20 +772,28 @@ def main() -> int:
         if not variants:
             print(f"unknown variant {args.only}", file=sys.stderr)
             return 2
-    # one untimed call per variant (it also builds the variant's workspace);
-    # the fastest listed colour count becomes the headline unless --colors names one
-    warm = {}
+    # every variant: one untimed call (it builds the variant's workspace and
+    # sizes the output buffer), then --variant-steps timed calls; the fastest
+    # listed colour count on those warm calls becomes the headline unless
+    # --colors names one
+    others = {}
     for c, fl in variants:
         name = "unfused" if fl else f"fused{c}"
         between_variants()
-        warm[name], cnt = timed_one(c, fl)
-        log(f"first call {name}: {warm[name] * 1e3:.2f} ms, members={cnt.members}")
+        dt0, cnt0 = timed_one(c, fl)
+        log(f"first call {name}: {dt0 * 1e3:.2f} ms, members={cnt0.members}")
+        s2, c2 = timed(c, fl, max(1, args.variant_steps))
+        others[name] = dict(samples_per_s=S / s2, ms_per_step=s2 * 1e3, steps=max(1, args.variant_steps),
+                            traversal_ms=sum(x.traversal_ns for x in c2) / len(c2) / 1e6,
+                            edge_accesses=c2[-1].edge_accesses, philox_blocks=c2[-1].philox_blocks,
+                            workgroups=c2[-1].workgroups)
+        log(f"{name}: {s2 * 1e3:.2f} ms/step")
 
-    fused_done = [c for c in w["colors"] if f"fused{c}" in warm]
+    fused_done = [c for c in w["colors"] if f"fused{c}" in others]
     if not fused_done:
         print("--only must name a fused variant (the headline is the fused traversal)", file=sys.stderr)
         return 2
-    colors = args.colors or min(fused_done, key=lambda c: warm[f"fused{c}"])
+    colors = args.colors or min(fused_done, key=lambda c: others[f"fused{c}"]["ms_per_step"])
     between_variants()
     for _ in range(max(1, args.warmup)):
         timed_one(colors, 0)
@@ -796,6 +804,9 @@ def main() -> int:
     te_per_s = cnt.sample_edges / sec
     trav_s = sum(c.traversal_ns for c in cnts) / len(cnts) / 1e9
     blocks = cnt.philox_blocks
+    others[f"fused{colors}"] = dict(samples_per_s=value, ms_per_step=sec * 1e3, steps=args.steps,
+                                    traversal_ms=trav_s * 1e3, edge_accesses=cnt.edge_accesses,
+                                    philox_blocks=blocks, workgroups=cnt.workgroups)
     # keep the headline output's sets that the oracle will recompute (every
     # cpu_stride-th sample id) for the parity check
     total = int(off[-1].item())
@@ -811,23 +822,6 @@ def main() -> int:
         pos += torch.arange(int(lens.sum().item()), device="cuda")
         gpu_sets = vert[pos].cpu().numpy().view(np.uint32).copy()
         del idx, lo, hi, lens, pos
-
-    others = {}
-    for c, fl in variants:
-        name = "unfused" if fl else f"fused{c}"
-        if not fl and c == colors:
-            others[name] = dict(samples_per_s=value, ms_per_step=sec * 1e3, steps=args.steps,
-                                traversal_ms=trav_s * 1e3, edge_accesses=cnt.edge_accesses,
-                                workgroups=cnt.workgroups)
-            continue
-        between_variants()
-        if big:
-            step(c, fl)  # re-create the workspace outside the timed steps
-        s2, c2 = timed(c, fl, max(1, args.variant_steps))
-        others[name] = dict(samples_per_s=S / s2, ms_per_step=s2 * 1e3, steps=max(1, args.variant_steps),
-                            traversal_ms=sum(x.traversal_ns for x in c2) / len(c2) / 1e6,
-                            edge_accesses=c2[-1].edge_accesses, workgroups=c2[-1].workgroups)
-        log(f"{name}: {s2 * 1e3:.2f} ms/step")
 
     # host-resident result (adds the device-to-host copy of the CSR over PCIe);
     # skipped when the result is too large to copy around in a benchmark
