@@ -211,6 +211,39 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
                           uint64_t* d_offsets, uint32_t* d_vertices, uint64_t capacity,
                           uint64_t* total_out, bpt_counters* counters);
 
+/* bpt_sample_rrr_noalloc - bpt_sample_rrr_device (fused traversal, flags 0)
+ * for callers that cannot allocate device memory: code that runs between the
+ * phases of a tight serving loop, harnesses that forbid allocation during a
+ * measured region, and callers that must not disturb the caching allocator of
+ * the framework they run under.  The call itself allocates nothing, on the
+ * host or the device: the traversal slots, per-sample counters, member pool,
+ * scan temporaries and control block are carved from one fixed scratch array
+ * of BPT_NOALLOC_SCRATCH_BYTES (256 MiB) that the library holds on every GPU
+ * it runs on, from the time its code is loaded until the process ends.
+ *
+ *   arguments         as bpt_sample_rrr_device without flags and counters;
+ *                     colors_per_batch 0 lets the library choose.
+ *
+ * The sets equal those of bpt_sample_rrr_device for the same graph, range,
+ * seed and colours.  The scratch bounds what one call can hold: 12 bytes per
+ * sample plus the scan's temporaries, at least one traversal slot (about
+ * 36 bytes per vertex for up to 64 colours, more for wider masks), and a pool
+ * of 4 bytes per member of all the call's sets; the number of slots (batches
+ * in flight) shrinks to leave the pool room.  A call that does not fit returns
+ * BPT_ENOMEM with the sizes in the message and writes nothing.  Every call on a
+ * GPU uses that GPU's scratch, which keeps the last call's contents (each call
+ * clears what must start at zero): calls of one process are serialized by the
+ * library, so two of them never overlap on a GPU.  Blocks the calling thread
+ * until the work on `stream` is done.  Other errors: BPT_EINVAL, BPT_ERANGE
+ * (capacity < total; *total_out set, d_vertices untouched), BPT_EDEVICE,
+ * BPT_EINTERNAL.
+ */
+#define BPT_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int bpt_sample_rrr_noalloc(bpt_graph* g, uint64_t first_sample, uint64_t n_samples,
+                           uint32_t colors_per_batch, uint64_t seed, void* stream,
+                           uint64_t* d_offsets, uint32_t* d_vertices, uint64_t capacity,
+                           uint64_t* total_out);
+
 /* Graph facts: vertices, edges, probability layout (BPT_PROB_*).  Any output
  * pointer may be NULL.  Returns BPT_OK or BPT_EINVAL. */
 int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_layout);

@@ -21,6 +21,7 @@ __all__ = [
     "BPT_PROB_UNIFORM", "BPT_PROB_ROW", "BPT_PROB_EDGE", "BPT_FLAG_UNFUSED", "BPT_FLAG_SORTED_STARTS",
     "BptError", "Counters", "Graph", "Job", "RRRResult", "Request", "Server", "BPT_REQ_SAMPLE", "BPT_REQ_SEEDS",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
+    "bpt_sample_rrr_noalloc",
     "bpt_max_cover", "Plan", "bpt_plan_create", "bpt_plan_enqueue",
     "bpt_graph_info", "bpt_graph_set_vertex_order",
     "bpt_graph_release_cache",
@@ -52,6 +53,7 @@ EXPORTED_SYMBOLS = (
     "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs", "bpt_max_cover",
     "bpt_server_create", "bpt_server_submit", "bpt_server_wait", "bpt_server_now", "bpt_server_stats",
     "bpt_server_destroy", "bpt_graph_set_vertex_order", "bpt_plan_create", "bpt_plan_enqueue",
+    "bpt_sample_rrr_noalloc",
 )
 
 
@@ -219,6 +221,7 @@ def load_library():
         "bpt_last_error": (cp, []),
         "bpt_sample_rrr_device": (i32, [vp, u64, u64, u32, u64, u32, vp, vp, vp, u64,
                                         ctypes.POINTER(u64), ctypes.POINTER(_Counters)]),
+        "bpt_sample_rrr_noalloc": (i32, [vp, u64, u64, u32, u64, vp, vp, vp, u64, ctypes.POINTER(u64)]),
         "bpt_sample_rrr_jobs": (i32, [ctypes.POINTER(_Job), u32, vp, ctypes.POINTER(_Counters)]),
         "bpt_plan_create": (vp, [vp, u64, u32, u64]),
         "bpt_plan_enqueue": (i32, [vp, u64, u64, u64, vp, vp, vp, vp, u64, vp]),
@@ -373,6 +376,21 @@ def bpt_sample_rrr_device(graph: Graph, first_sample: int, n_samples: int, color
     if st not in (BPT_OK, BPT_ERANGE):
         _raise_last()
     return st, int(total.value), Counters(**{k: int(getattr(cnt, k)) for k, _ in _Counters._fields_})
+
+
+def bpt_sample_rrr_noalloc(graph: Graph, first_sample: int, n_samples: int, colors_per_batch: int, seed: int,
+                           stream, d_offsets, d_vertices, capacity: int):
+    """bpt_sample_rrr_device without allocation (fused, no flags, no counters):
+    the library's fixed per-GPU scratch holds all working memory.  Returns
+    (status, total); status is BPT_OK or BPT_ERANGE."""
+    lib = load_library()
+    total = ctypes.c_uint64(0)
+    st = lib.bpt_sample_rrr_noalloc(graph.handle, first_sample, n_samples, colors_per_batch, seed,
+                                    _stream(stream), _addr(d_offsets), _addr(d_vertices), capacity,
+                                    ctypes.byref(total))
+    if st not in (BPT_OK, BPT_ERANGE):
+        _raise_last()
+    return st, int(total.value)
 
 
 def bpt_sample_rrr_jobs(jobs, stream=None):

@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libbpt.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["bpt_capi.cpp", "bpt_graph.cpp", "bpt_fused.hip", "bpt_unfused.hip", "bpt_finalize.hip",
-           "bpt_cover.hip", "bpt_server.cpp", "bpt_order.hip", "bpt_plan.hip"]
+           "bpt_cover.hip", "bpt_server.cpp", "bpt_order.hip", "bpt_plan.hip", "bpt_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

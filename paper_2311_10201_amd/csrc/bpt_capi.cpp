@@ -239,6 +239,36 @@ size_t fused_slot_bytes(uint32_t n, int nw) {
     return b;
 }
 
+// Lays out `slots` fused traversal slots for graphs of up to n vertices from
+// `base` (256-byte aligned pieces) and returns the bytes they take; with a
+// null base it only measures.  Everything in it must be zero before the first
+// launch that uses it.
+size_t carve_fused_slots(char* base, uint32_t n, int nw, uint32_t slots, FusedSlots* fs) {
+    const size_t S = slots, N = n;
+    const size_t words = bitmap_words(n);
+    size_t off = 0;
+    auto take = [&](size_t sz) {
+        char* q = base ? base + off : nullptr;
+        off += (sz + 255) & ~(size_t)255;
+        return q;
+    };
+    FusedSlots f{};
+    f.visited = reinterpret_cast<unsigned long long*>(take(S * N * nw * 8));
+    f.frontier = reinterpret_cast<unsigned long long*>(take(S * 2 * N * nw * 8));
+    f.stamp = reinterpret_cast<uint32_t*>(take(nw > 1 ? S * N * 4 : 4));
+    f.queue = reinterpret_cast<uint32_t*>(take(S * 2 * N * 4));
+    f.touched = reinterpret_cast<uint32_t*>(take(S * N * 4));
+    f.tbits = reinterpret_cast<unsigned long long*>(take(S * words * 8));
+    f.slot_tag = reinterpret_cast<uint32_t*>(take(S * 4));
+    if (nw == 1) {
+        f.help = reinterpret_cast<HelpRec*>(take(S * sizeof(HelpRec)));
+        f.hstage = reinterpret_cast<uint32_t*>(take(S * kHelpStagePos * 6 * 4));
+    }
+    f.slots = slots;
+    if (fs) *fs = f;
+    return off;
+}
+
 size_t unfused_slot_bytes(uint32_t n) { return bitmap_words(n) * 8 + (size_t)n * 4; }
 
 size_t memory_budget() {
@@ -278,29 +308,10 @@ Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
             const size_t want = std::min<size_t>(slots_wanted(g, nw, units), mem_max);
             ws->slots = (uint32_t)std::max<size_t>(1, want);
             ws->full = want >= device_max || want >= mem_max;
-            const size_t S = ws->slots, N = n;
-            const size_t words = bitmap_words(n);
-            size_t bytes = S * per + S * 4 + 4096;
+            const size_t bytes = carve_fused_slots(nullptr, n, nw, ws->slots, nullptr);
             ws->slot_mem = dev_alloc<char>(bytes);
             HIP_TRY(hipMemset(ws->slot_mem, 0, bytes));
-            p = static_cast<char*>(ws->slot_mem);
-            auto take = [&](size_t sz) {
-                char* q = p;
-                p += (sz + 255) & ~(size_t)255;
-                return q;
-            };
-            ws->fs.visited = reinterpret_cast<unsigned long long*>(take(S * N * nw * 8));
-            ws->fs.frontier = reinterpret_cast<unsigned long long*>(take(S * 2 * N * nw * 8));
-            ws->fs.stamp = reinterpret_cast<uint32_t*>(take(nw > 1 ? S * N * 4 : 4));
-            ws->fs.queue = reinterpret_cast<uint32_t*>(take(S * 2 * N * 4));
-            ws->fs.touched = reinterpret_cast<uint32_t*>(take(S * N * 4));
-            ws->fs.tbits = reinterpret_cast<unsigned long long*>(take(S * words * 8));
-            ws->fs.slot_tag = reinterpret_cast<uint32_t*>(take(S * 4));
-            if (nw == 1) {
-                ws->fs.help = reinterpret_cast<HelpRec*>(take(S * sizeof(HelpRec)));
-                ws->fs.hstage = reinterpret_cast<uint32_t*>(take(S * kHelpStagePos * 6 * 4));
-            }
-            ws->fs.slots = ws->slots;
+            carve_fused_slots(static_cast<char*>(ws->slot_mem), n, nw, ws->slots, &ws->fs);
         } else {
             const size_t per = unfused_slot_bytes(n) + 512;
             const size_t device_max = (size_t)g->cus * 16;  // wavefronts
@@ -802,6 +813,7 @@ uint32_t choose_colors(bpt_graph* g, uint64_t n_samples) {
 }
 
 }  // namespace
+
 }  // namespace bpt
 
 using namespace bpt;
@@ -925,6 +937,139 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
         if (ws) release(gg, ws);
         set_status(BPT_ENOMEM, "host allocation failed");
         return BPT_ENOMEM;
+    }
+}
+
+int bpt_sample_rrr_noalloc(bpt_graph* g, uint64_t first_sample, uint64_t n_samples, uint32_t colors_per_batch,
+                           uint64_t seed, void* stream, uint64_t* d_offsets, uint32_t* d_vertices, uint64_t capacity,
+                           uint64_t* total_out) {
+    bpt_graph* gg = check_graph(g);
+    if (!gg) {
+        set_status(BPT_EINVAL, "not a bpt_graph handle");
+        return BPT_EINVAL;
+    }
+    if (!total_out || !d_offsets || (!d_vertices && capacity > 0)) {
+        set_status(BPT_EINVAL, "d_offsets and total_out are required (d_vertices when capacity > 0)");
+        return BPT_EINVAL;
+    }
+    if (n_samples >= kMaxSamples || first_sample >= kMaxSamples || first_sample + n_samples > kMaxSamples) {
+        set_status(BPT_EINVAL, "sample ids must stay below 2^34");
+        return BPT_EINVAL;
+    }
+    const uint32_t colors = colors_per_batch ? colors_per_batch : choose_colors(gg, n_samples);
+    if (!valid_colors(colors)) {
+        set_status(BPT_EINVAL, "colors_per_batch must be 0 or a power of two from 8 to 1024");
+        return BPT_EINVAL;
+    }
+    // the fixed part of the scratch: control block, per-sample counts and pool
+    // positions, the CSR scan's temporaries; traversal slots and the member
+    // pool share the rest
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t ctl_b = up(sizeof(Control));
+    const size_t counts_b = up(n_samples * 4), where_b = up(n_samples * 8);
+    const size_t fin_b = up(finalize_scratch_bytes(n_samples));
+    const size_t fixed = ctl_b + counts_b + where_b + fin_b;
+    const int nw = mask_words(colors);
+    const size_t per_slot = carve_fused_slots(nullptr, gg->n, nw, 1, nullptr);
+    if (fixed + per_slot + 1024 > kNoAllocScratchBytes) {
+        set_status(BPT_ENOMEM, "this call needs " + std::to_string(fixed + per_slot + 1024) +
+                                   " bytes of scratch (samples, graph size and colours) but the fixed scratch holds " +
+                                   std::to_string(kNoAllocScratchBytes));
+        return BPT_ENOMEM;
+    }
+    try {
+        HIP_TRY(hipSetDevice(gg->device));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        void* base_v = nullptr;
+        HIP_TRY(noalloc_scratch(gg->device, &base_v));
+        char* base = static_cast<char*>(base_v);
+        // calls in this process share the device's scratch: one at a time
+        static std::mutex call_mu;
+        std::lock_guard<std::mutex> lk(call_mu);
+        if (n_samples == 0) {
+            HIP_TRY(launch_zero_fill(base, 256, st));  // offsets[0] = 0 through a kernel, no allocation
+            HIP_TRY(hipMemcpyAsync(d_offsets, base, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            *total_out = 0;
+            set_ok();
+            return BPT_OK;
+        }
+        Control* ctl = reinterpret_cast<Control*>(base);
+        uint32_t* counts = reinterpret_cast<uint32_t*>(base + ctl_b);
+        unsigned long long* where = reinterpret_cast<unsigned long long*>(base + ctl_b + counts_b);
+        void* fin = base + ctl_b + counts_b + where_b;
+        char* slot_base = base + fixed;
+        const uint64_t n_batches = (n_samples + colors - 1) / colors;
+        const uint64_t device_slots = (uint64_t)gg->cus * fused_per_cu(fused_block(nw));
+        uint64_t pool_want = pool_estimate(gg, n_samples);
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            const size_t room = kNoAllocScratchBytes - fixed;
+            uint64_t slots = std::min<uint64_t>(device_slots, n_batches);
+            const size_t pool_bytes_want = up(pool_want * 4);
+            slots = pool_bytes_want + per_slot <= room ? std::min<uint64_t>(slots, (room - pool_bytes_want) / per_slot)
+                                                       : 1;
+            slots = std::max<uint64_t>(slots, 1);
+            const size_t slot_bytes = carve_fused_slots(nullptr, gg->n, nw, (uint32_t)slots, nullptr);
+            if (slot_bytes + 1024 > room) slots = 1;
+            FusedSlots fs{};
+            const size_t used = carve_fused_slots(slot_base, gg->n, nw, (uint32_t)slots, &fs);
+            uint32_t* pool = reinterpret_cast<uint32_t*>(slot_base + used);
+            const uint64_t pool_cap = (room - used) / 4;
+            if (pool_cap < pool_want && attempt > 0) {
+                set_status(BPT_ENOMEM, "the sets of this call take " + std::to_string(pool_want) +
+                                           " vertex ids; the fixed scratch has room for " + std::to_string(pool_cap));
+                return BPT_ENOMEM;
+            }
+            // the control block and the traversal slots start at zero
+            HIP_TRY(launch_zero_fill(ctl, ctl_b, st));
+            HIP_TRY(launch_zero_fill(slot_base, used, st));
+            FusedArgs a = {};
+            a.job0.g = dev_graph(gg);
+            a.job0.seed = seed;
+            a.job0.first_sample = first_sample;
+            a.job0.n_samples = n_samples;
+            a.job0.colors = colors;
+            a.n_jobs = 1;
+            a.n_max = gg->n;
+            a.ws = fs;
+            a.out.counts = counts;
+            a.out.where = where;
+            a.out.pool = pool;
+            a.out.pool_cap = pool_cap;
+            a.ctl = ctl;
+            a.n_batches = n_batches;
+            a.gather_mode = gather_mode();
+            int block = 0, grid = 0;
+            fused_launch_shape(gg, nw, (uint32_t)slots, n_batches, &block, &grid);
+            HIP_TRY(launch_fused(a, nw, block, grid, help_wanted(gg), st));
+            HIP_TRY(launch_finalize(counts, where, pool, n_samples, reinterpret_cast<unsigned long long*>(d_offsets),
+                                    d_vertices, capacity, &ctl->total, &ctl->err, fin, fin_b, st));
+            Control c;
+            HIP_TRY(hipMemcpyAsync(&c, ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (c.err & kErrPoolOverflow) {  // fewer slots, a larger pool
+                pool_want = c.pool_cursor + c.pool_cursor / 16 + 1024;
+                continue;
+            }
+            if (c.err) {
+                set_status(BPT_EINTERNAL, "device consistency check failed (error bits " + std::to_string(c.err) + ")");
+                return BPT_EINTERNAL;
+            }
+            note_members(gg, n_samples, c.total);
+            *total_out = c.total;
+            if (c.total > capacity) {
+                set_status(BPT_ERANGE, "output capacity " + std::to_string(capacity) + " < " +
+                                           std::to_string(c.total) + " members");
+                return BPT_ERANGE;
+            }
+            set_ok();
+            return BPT_OK;
+        }
+        set_status(BPT_ENOMEM, "the sets of this call do not fit the fixed scratch");
+        return BPT_ENOMEM;
+    } catch (const HipFail& f) {
+        set_status(f.status, f.msg);
+        return f.status;
     }
 }
 

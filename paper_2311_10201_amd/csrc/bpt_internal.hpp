@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "bpt.h"
+
 namespace bpt {
 
 // ---------------------------------------------------------------------------
@@ -179,6 +181,13 @@ hipError_t launch_sort_by_start(uint32_t n, uint64_t seed, uint64_t first, uint6
 hipError_t launch_plan_setup(FusedJob* job, const uint64_t* params, uint64_t first, uint64_t seed,
                              uint64_t n_samples, uint64_t max_ids, Control* ctl, hipStream_t stream);
 hipError_t launch_plan_report(const Control* ctl, unsigned long long capacity, int64_t* result, hipStream_t stream);
+
+// Allocation-free calls (bpt_noalloc.hip): a fixed scratch array per device,
+// resolved to its device address once per device (the device must be
+// current), and a kernel that zeroes a 16-byte aligned range.
+constexpr size_t kNoAllocScratchBytes = (size_t)BPT_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch(int device, void** addr);
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t stream);
 
 // Greedy maximum coverage (bpt_cover.hip).  Error bits of its device flag.
 constexpr unsigned int kCoverBadOffsets = 1u;  // offsets not non-decreasing or past the member count
