@@ -53,6 +53,11 @@ constexpr int ept(int nw, int bs) {
     return nw == 1 ? (bs <= 512 ? 4 : 2) : (nw == 2 ? (bs <= 256 ? 4 : 2) : (nw == 4 && bs <= 256 ? 2 : 1));
 }
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Live coins a wavefront queues in LDS before resolving them: their source
+// ids are loaded and their discoveries performed 64 at a time, one per lane,
+// so the dependent global round trips of a discovery are paid once per 64
+// live coins instead of once per coin loop of every lane that drew one.
+constexpr uint32_t kDiscQueue = 256;
 constexpr uint32_t kQuadsPerItem = 8;  // 4-edge quads one work item covers at most (one entry lookup)
 
 // 4-edge quads per work item of an entry with pc colours: kQuadsPerItem in
@@ -106,9 +111,23 @@ struct FusedShared {
     uint32_t scan_tmp[2][BS / kWave];
     unsigned long long base;
     unsigned long long stats[kNumStats];
+    // live coins waiting for discovery, per wavefront: edge id and colour
+    uint32_t dq_e[BS / kWave][kDiscQueue];
+    uint16_t dq_c[BS / kWave][kDiscQueue];
+    uint32_t dq_len[BS / kWave];
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Values every lane of the wavefront holds alike, moved to scalar registers.
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
+}
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+    return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
+}
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const uint32_t lane = lane_id();
@@ -429,11 +448,22 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
             }
             n_philox += nq;
             live &= valid;
-            while (live) {
-                const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
-                live &= live - 1;
-                ++n_live;
-                discover<NW, kSh>(b, ct, g.col[e_first + j], c, nxt, qslot, tag, base_tag);
+            if (live) {  // queue the live coins; past the queue's end, discover directly
+                const uint32_t k = (uint32_t)__popc(live);
+                const uint32_t wid = threadIdx.x / kWave;
+                uint32_t p = atomicAdd(&s.dq_len[wid], k);
+                n_live += k;
+                while (live) {
+                    const uint32_t j = (uint32_t)(__ffs((int)live) - 1);
+                    live &= live - 1;
+                    if (p < kDiscQueue) {
+                        s.dq_e[wid][p] = e_first + j;
+                        s.dq_c[wid][p] = (uint16_t)c;
+                    } else {
+                        discover<NW, kSh>(b, ct, g.col[e_first + j], c, nxt, qslot, tag, base_tag);
+                    }
+                    ++p;
+                }
             }
         }
     }
@@ -448,6 +478,37 @@ __device__ __forceinline__ uint32_t find_entry(const uint32_t* scan, uint32_t cn
         else hi = mid;
     }
     return lo;
+}
+
+// Resolves the wavefront's queued live coins: every full group of 64 (all of
+// them when `all`), one coin per lane (source id, then the discovery).  Called
+// by every lane of the wavefront at the same point; the rest stays queued.
+template <int NW, int BS, bool kSh>
+__device__ __forceinline__ void drain_queue(const DevGraph& g, const BatchCtx<NW>& b, FusedShared<NW, BS>& s,
+                                            const Ctr& ct, int nxt, uint32_t qslot, uint32_t tag, uint32_t base_tag,
+                                            bool all) {
+    const uint32_t wid = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t len = uni32(min(s.dq_len[wid], kDiscQueue));
+    const uint32_t upto = all ? len : len & ~(kWave - 1);
+    if (upto == 0) return;
+    for (uint32_t d = 0; d < upto; d += kWave) {
+        const uint32_t i = d + lane;
+        if (i < upto) discover<NW, kSh>(b, ct, g.col[s.dq_e[wid][i]], (uint32_t)s.dq_c[wid][i], nxt, qslot, tag,
+                                        base_tag);
+    }
+    const uint32_t rem = len - upto;  // fewer than 64, moved to the front
+    uint32_t e = 0, c = 0;
+    if (lane < rem) {
+        e = s.dq_e[wid][upto + lane];
+        c = s.dq_c[wid][upto + lane];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rem) {
+        s.dq_e[wid][lane] = e;
+        s.dq_c[wid][lane] = (uint16_t)c;
+    }
+    if (lane == 0) s.dq_len[wid] = rem;
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Work item t of the chunk staged in LDS (npos positions).
@@ -560,15 +621,6 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
     }
 }
 
-// Values every lane of the wavefront holds alike, moved to scalar registers.
-__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-    return ((uint64_t)uni32((uint32_t)(x >> 32)) << 32) | uni32((uint32_t)x);
-}
-template <class T>
-__device__ __forceinline__ T* uni_ptr(T* p) {
-    return reinterpret_cast<T*>(uni64(reinterpret_cast<uint64_t>(p)));
-}
 
 // The job data of launch-wide batch bt (of job `job`), in scalar registers.
 struct BatchJob {
@@ -710,6 +762,7 @@ __device__ void help_others(const FusedArgs& a, FusedShared<NW, BS>& s, uint32_t
             if (t < total)
                 run_item<NW, BS, true>(jb.g, jb.seed, a.gather_mode, b, s, ct, s0, jb.first, false, t, s.h_npos,
                                        (int)s.h_nxt, s.h_qnext, 0u, 0u, th_philox, th_live);
+            drain_queue<NW, BS, true>(jb.g, b, s, ct, (int)s.h_nxt, s.h_qnext, 0u, 0u, true);
             if (th_philox >= 0x80000000u || th_live >= 0x80000000u) {
                 atomicAdd(&s.stats[kStatPhilox], (unsigned long long)th_philox);
                 atomicAdd(&s.stats[kStatLive], (unsigned long long)th_live);
@@ -741,6 +794,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
     HelpRec* const hr = (kHelp && NW == 1 && a.ws.help) ? a.ws.help + slot : nullptr;
 
     if (tid < kNumStats) s.stats[tid] = 0;
+    if (tid < BS / kWave) s.dq_len[tid] = 0;
     if (tid == 0) {
         s.tail = 0;
         s.probes = 0;
@@ -981,12 +1035,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                         __syncthreads();
                         if ((unsigned long long)unit * BS >= total) break;
                         const uint32_t t = unit * BS + tid;
+                        const Ctr ct_help{hr->qlen, &hr->tlen, s.cnt};
                         if (t < total)
-                            run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, s0,
-                                                   first, ordered, t, npos, nxt, qnext, tag, base_tag, th_philox,
-                                                   th_live);
+                            run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, ct_help, s0, first, ordered, t, npos,
+                                                   nxt, qnext, tag, base_tag, th_philox, th_live);
+                        drain_queue<NW, BS, true>(g, b, s, ct_help, nxt, qnext, tag, base_tag, false);
                         mine += min((uint32_t)BS, total - unit * BS);
                     }
+                    drain_queue<NW, BS, true>(g, b, s, Ctr{hr->qlen, &hr->tlen, s.cnt}, nxt, qnext, tag, base_tag,
+                                              true);
                     wait_own_memory_ops();
                     __syncthreads();
                     if (tid == 0) {  // wait for the units helpers claimed
@@ -1003,13 +1060,21 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                         s.tlen = load_coherent32(&hr->tlen);
                     }
                 } else if (shared) {  // alone, counters in LDS, entries written coherently
-                    for (uint32_t t = tid; t < total; t += BS)
-                        run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t, npos, nxt,
-                                               qnext, tag, base_tag, th_philox, th_live);
+                    for (uint32_t t0 = 0; t0 < total; t0 += BS) {
+                        if (t0 + tid < total)
+                            run_item<NW, BS, true>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t0 + tid,
+                                                   npos, nxt, qnext, tag, base_tag, th_philox, th_live);
+                        drain_queue<NW, BS, true>(g, b, s, ct_own, nxt, qnext, tag, base_tag, false);
+                    }
+                    drain_queue<NW, BS, true>(g, b, s, ct_own, nxt, qnext, tag, base_tag, true);
                 } else {
-                    for (uint32_t t = tid; t < total; t += BS)
-                        run_item<NW, BS, false>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t, npos,
-                                                nxt, qnext, tag, base_tag, th_philox, th_live);
+                    for (uint32_t t0 = 0; t0 < total; t0 += BS) {
+                        if (t0 + tid < total)
+                            run_item<NW, BS, false>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t0 + tid,
+                                                    npos, nxt, qnext, tag, base_tag, th_philox, th_live);
+                        drain_queue<NW, BS, false>(g, b, s, ct_own, nxt, qnext, tag, base_tag, false);
+                    }
+                    drain_queue<NW, BS, false>(g, b, s, ct_own, nxt, qnext, tag, base_tag, true);
                 }
                 set_wave_priority(0);
                 if (th_philox >= 0x80000000u || th_live >= 0x80000000u) {
