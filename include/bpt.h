@@ -364,14 +364,24 @@ int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_
                   void* stream, uint32_t* seeds, uint64_t* gains);
 
 /* ------------------------------------------------------------------------
- * Serving loop.  A server owns one worker thread on the graphs' device.
- * Requests submitted from any thread are queued; each worker iteration
- * admits queued requests in arrival order while their estimated memory (the
- * sets' expected size from a running per-graph mean, plus per-sample arrays)
- * fits the budget, always at least one, and at most max_jobs_per_launch;
- * samples all of them with one bpt_sample_rrr_jobs call; runs bpt_max_cover
- * for the seed requests; and moves them to a completion queue.  Every
- * request gets the result it would get alone.
+ * Serving loop with continuous batching (paper Section 2: influence
+ * maximization by greedy maximum coverage over sampled RRR sets).  A server
+ * owns a worker thread on the device that was current when it was created,
+ * and a second thread for seed selection.  Requests submitted from any thread
+ * are queued; the worker admits them in arrival order while their estimated
+ * memory (the sets' expected size from a running per-graph mean, plus
+ * per-sample arrays) fits the budget, always one when nothing runs.  The GPU
+ * is fed a pipeline of bounded persistent launches on two streams: each
+ * launch takes the next batches of every admitted request, an equal share
+ * each, about two batches per resident workgroup in all (at most
+ * max_jobs_per_launch requests), and the next launch is enqueued while the
+ * current one drains.  A request that arrives while others are on the GPU
+ * therefore joins the next launch and shares it with them.  Each chunk's CSR
+ * is appended to its request's output in sample order; a request completes
+ * when its last chunk has, and seed requests then run bpt_max_cover on the
+ * second thread while sampling continues.  Every request gets exactly the
+ * result it would get alone.  Colour counts are bpt_default_colors capped
+ * at 64.
  * ---------------------------------------------------------------------- */
 typedef struct bpt_server bpt_server;
 
@@ -393,15 +403,19 @@ typedef struct bpt_request {
     uint64_t* gains;          /* in (SEEDS): host, k entries, written                */
     uint64_t total;           /* out: members of the request's sets                  */
     int32_t status;           /* out: 1 while in flight, then BPT_OK or an error
-                                 (BPT_ERANGE: SAMPLE capacity below total)           */
+                                 (BPT_ERANGE: SAMPLE capacity below total; offsets
+                                 valid, members written only up to the capacity)    */
     uint32_t reserved;
     double t_submit;          /* out: server clock (bpt_server_now), seconds         */
     double t_start;           /* out: its launch began                               */
     double t_done;            /* out: completed                                      */
 } bpt_request;
 
-/* memory_budget: bytes of admitted work per launch (0: 8 GiB);
- * max_jobs_per_launch: 0 for 256.  NULL on failure. */
+/* memory_budget: bytes of admitted work at a time (0: 8 GiB);
+ * max_jobs_per_launch: requests sharing one launch at most, 0 for 256.
+ * Device memory: two traversal workspaces sized for the largest graph seen
+ * (about 36 bytes per vertex per resident workgroup each) and their pools.
+ * NULL on failure. */
 bpt_server* bpt_server_create(uint64_t memory_budget, uint32_t max_jobs_per_launch);
 /* Queues r; r must stay valid until bpt_server_wait returns it.  BPT_EINVAL
  * for a bad server or request (missing buffers, k = 0, unknown kind). */
@@ -412,12 +426,12 @@ bpt_request* bpt_server_wait(bpt_server* s, double timeout_s);
 double bpt_server_now(bpt_server* s);
 /* What the worker has done so far. */
 typedef struct bpt_server_info {
-    uint64_t launches; /* bpt_sample_rrr_jobs calls                          */
+    uint64_t launches; /* fused launches issued                              */
     uint64_t served;   /* requests completed                                 */
-    double busy_s;     /* worker time serving groups, seconds                */
-    double sample_s;   /* ... of which in the sampling calls                 */
-    double cover_s;    /* ... in seed selection (incl. its output's release) */
-    double alloc_s;    /* ... allocating seed requests' set buffers          */
+    double busy_s;     /* wall time with admitted requests, seconds          */
+    double sample_s;   /* ... of which with a launch in flight               */
+    double cover_s;    /* seed-selection time (second thread)                */
+    double alloc_s;    /* time getting seed requests' set buffers            */
 } bpt_server_info;
 int bpt_server_stats(bpt_server* s, bpt_server_info* out);
 /* Serves what is queued, then stops the worker and frees the server. */

@@ -13,6 +13,7 @@
 #include "bpt.h"
 #include "bpt_host.hpp"
 #include "bpt_internal.hpp"
+#include "bpt_lane.hpp"
 #include "bpt_rng.hpp"
 
 #define BPT_VERSION_STRING "libbpt 0.1 (gfx950)"
@@ -814,6 +815,198 @@ uint32_t choose_colors(bpt_graph* g, uint64_t n_samples) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Lanes: pipelined chunk launches of the serving loop (bpt_lane.hpp).
+// ---------------------------------------------------------------------------
+struct Lane {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Workspace* ws = nullptr;
+    uint32_t ws_n = 0;          // vertices per slot of ws
+    uint64_t pool_floor = 0;    // pool entries the last overflow showed to be needed
+    bool pending = false;       // a launch was enqueued and not yet waited for
+};
+
+Lane* lane_create(int device, std::string* why) {
+    Lane* l = new (std::nothrow) Lane();
+    if (!l) {
+        *why = "host allocation failed";
+        return nullptr;
+    }
+    l->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking) != hipSuccess ||  // default priority
+        hipEventCreateWithFlags(&l->done, hipEventDisableTiming) != hipSuccess) {
+        *why = "stream or event creation failed";
+        lane_destroy(l);
+        return nullptr;
+    }
+    return l;
+}
+
+void lane_destroy(Lane* l) {
+    if (!l) return;
+    if (l->stream) (void)hipStreamSynchronize(l->stream);
+    delete l->ws;
+    if (l->done) (void)hipEventDestroy(l->done);
+    if (l->stream) (void)hipStreamDestroy(l->stream);
+    delete l;
+}
+
+hipStream_t lane_stream(Lane* l) { return l->stream; }
+hipEvent_t lane_done(Lane* l) { return l->done; }
+
+bool lane_finished(Lane* l) { return !l->pending || hipEventQuery(l->done) == hipSuccess; }
+
+int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, std::string* why) {
+    if (l->pending) {
+        *why = "the lane's previous launch was not waited for";
+        return BPT_EINVAL;
+    }
+    if (n == 0) return BPT_OK;
+    try {
+        HIP_TRY(hipSetDevice(l->device));
+        bpt_graph* owner = nullptr;
+        uint64_t n_batches = 0, total_samples = 0, est = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const LaneChunk& c = chunks[i];
+            if (!valid_colors(c.colors) || c.colors > 64 || c.n_samples == 0) {
+                *why = "lane chunks take 8 to 64 colours and at least one sample";
+                return BPT_EINVAL;
+            }
+            if (!owner || c.graph->n > owner->n) owner = c.graph;
+            n_batches += (c.n_samples + c.colors - 1) / c.colors;
+            total_samples += c.n_samples;
+            est += pool_estimate(c.graph, c.n_samples);
+        }
+        if (!l->ws || l->ws_n < owner->n) {  // slots for the largest graph so far, as many as the GPU keeps resident
+            delete l->ws;
+            l->ws = nullptr;
+            l->ws = make_workspace(owner, 1, ~0ull >> 1);
+            l->ws_n = owner->n;
+        }
+        Workspace* ws = l->ws;
+        ensure_sample_arrays(ws, total_samples);
+        ensure_jobs(ws, n);
+        if (ws->pool_cap < std::max(est, l->pool_floor)) ensure_pool(owner, ws, std::max(est, l->pool_floor) * 2);
+        uint64_t b = 0, base = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const LaneChunk& c = chunks[i];
+            FusedJob& fj = ws->h_jobs[i];
+            fj = FusedJob{};
+            fj.g = dev_graph(c.graph);
+            fj.seed = c.seed;
+            fj.first_sample = c.first_sample;
+            fj.n_samples = c.n_samples;
+            fj.batch_begin = b;
+            fj.out_base = base;
+            fj.colors = c.colors;
+            b += (c.n_samples + c.colors - 1) / c.colors;
+            base += c.n_samples;
+        }
+        HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), l->stream));
+        HIP_TRY(hipMemcpyAsync(ws->d_jobs, ws->h_jobs, n * sizeof(FusedJob), hipMemcpyHostToDevice, l->stream));
+        FusedArgs a = {};
+        a.jobs = ws->d_jobs;
+        a.n_jobs = n;
+        a.n_max = l->ws_n;
+        a.ws = ws->fs;
+        a.out.counts = ws->counts;
+        a.out.where = ws->where;
+        a.out.pool = ws->pool;
+        a.out.pool_cap = ws->pool_cap;
+        a.ctl = ws->ctl;
+        a.n_batches = n_batches;
+        a.gather_mode = gather_mode();
+        int block = 0, grid = 0;
+        fused_launch_shape(owner, 1, ws->slots, n_batches, &block, &grid);
+        // no tail helping: idle workgroups leave at once, so that the next
+        // launch (on the other lane) takes their place while this one drains
+        HIP_TRY(launch_fused(a, 1, block, grid, false, l->stream));
+        if (after) HIP_TRY(hipStreamWaitEvent(l->stream, after, 0));
+        for (uint32_t i = 0; i < n; ++i) {
+            const LaneChunk& c = chunks[i];
+            const uint64_t ob = ws->h_jobs[i].out_base;
+            HIP_TRY(launch_finalize(ws->counts + ob, ws->where + ob, ws->pool, c.n_samples, c.d_offsets,
+                                    c.d_vertices, c.capacity, c.d_total, &ws->ctl->err, ws->scratch,
+                                    ws->scratch_bytes, l->stream, c.d_total));
+        }
+        HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, l->stream));
+        HIP_TRY(hipEventRecord(l->done, l->stream));
+        l->pending = true;
+        return BPT_OK;
+    } catch (const HipFail& f) {
+        *why = f.msg;
+        return f.status;
+    } catch (const std::bad_alloc&) {
+        *why = "host allocation failed";
+        return BPT_ENOMEM;
+    }
+}
+
+int lane_wait(Lane* l, bool* overflow, std::string* why) {
+    *overflow = false;
+    if (!l->pending) return BPT_OK;
+    l->pending = false;
+    const hipError_t e = hipEventSynchronize(l->done);
+    if (e != hipSuccess) {
+        *why = std::string("hipEventSynchronize: ") + hipGetErrorString(e);
+        return BPT_EDEVICE;
+    }
+    const Control& c = *l->ws->ctl_host;
+    if (c.err & kErrPoolOverflow) {
+        *overflow = true;
+        l->pool_floor = c.pool_cursor + c.pool_cursor / 8 + 1024;
+    }
+    if (c.err & ~(unsigned)kErrPoolOverflow) {
+        *why = "device consistency check failed (error bits " + std::to_string(c.err) + ")";
+        delete l->ws;  // its traversal state may not be clean
+        l->ws = nullptr;
+        l->ws_n = 0;
+        return BPT_EINTERNAL;
+    }
+    return BPT_OK;
+}
+
+size_t max_cover_scratch(uint64_t n_sets, uint32_t n, uint32_t k) { return max_cover_scratch_bytes(n_sets, n, k); }
+
+int max_cover_run(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
+                  hipStream_t st, uint32_t* seeds, uint64_t* gains, void* scratch, std::string* why) {
+    if (!d_offsets || !seeds || !gains || n == 0 || k > n || n_sets >= (1ull << 32)) {
+        *why = "d_offsets, seeds and gains are required; 1 <= n, k <= n, n_sets < 2^32";
+        return BPT_EINVAL;
+    }
+    if (k == 0) return BPT_OK;
+    try {
+        uint64_t total = 0;
+        HIP_TRY(hipMemcpyAsync(&total, d_offsets + n_sets, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (total > 0 && !d_vertices) {
+            *why = "d_vertices is required when the sets have members";
+            return BPT_EINVAL;
+        }
+        uint32_t* seeds_dev = nullptr;
+        unsigned long long* gains_dev = nullptr;
+        unsigned int* bad_dev = nullptr;
+        HIP_TRY(launch_max_cover(d_offsets, d_vertices, n_sets, total, n, k, scratch, &seeds_dev, &gains_dev,
+                                 &bad_dev, st));
+        unsigned int bad = 0;
+        HIP_TRY(hipMemcpyAsync(seeds, seeds_dev, (size_t)k * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(gains, gains_dev, (size_t)k * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&bad, bad_dev, sizeof(bad), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (bad) {
+            *why = (bad & kCoverBadOffsets) ? "offsets are not a CSR of the vertex array" : "a set member is >= n";
+            return BPT_EINVAL;
+        }
+    } catch (const HipFail& f) {
+        *why = f.msg;
+        return f.status;
+    }
+    return BPT_OK;
+}
+
 }  // namespace bpt
 
 using namespace bpt;
@@ -1250,37 +1443,17 @@ int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_
         return BPT_OK;
     }
     void* scratch = nullptr;
-    try {
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        uint64_t total = 0;
-        HIP_TRY(hipMemcpyAsync(&total, d_offsets + n_sets, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (total > 0 && !d_vertices) {
-            set_status(BPT_EINVAL, "d_vertices is required when the sets have members");
-            return BPT_EINVAL;
-        }
-        HIP_TRY(hipMalloc(&scratch, max_cover_scratch_bytes(n_sets, n, k)));
-        uint32_t* seeds_dev = nullptr;
-        unsigned long long* gains_dev = nullptr;
-        unsigned int* bad_dev = nullptr;
-        HIP_TRY(launch_max_cover(d_offsets, d_vertices, n_sets, total, n, k, scratch, &seeds_dev, &gains_dev,
-                                 &bad_dev, st));
-        unsigned int bad = 0;
-        HIP_TRY(hipMemcpyAsync(seeds, seeds_dev, (size_t)k * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(gains, gains_dev, (size_t)k * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(&bad, bad_dev, sizeof(bad), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        HIP_TRY(hipFree(scratch));
-        scratch = nullptr;
-        if (bad) {
-            set_status(BPT_EINVAL, (bad & kCoverBadOffsets) ? "offsets are not a CSR of the vertex array"
-                                                            : "a set member is >= n");
-            return BPT_EINVAL;
-        }
-    } catch (const HipFail& f) {
-        if (scratch) (void)hipFree(scratch);
-        set_status(f.status, f.msg);
-        return f.status;
+    if (hipMalloc(&scratch, max_cover_scratch_bytes(n_sets, n, k)) != hipSuccess) {
+        set_status(BPT_ENOMEM, "device scratch of the coverage greedy");
+        return BPT_ENOMEM;
+    }
+    std::string why;
+    const int rc = max_cover_run(d_offsets, d_vertices, n_sets, n, k, static_cast<hipStream_t>(stream), seeds, gains,
+                                 scratch, &why);
+    (void)hipFree(scratch);
+    if (rc != BPT_OK) {
+        set_status(rc, why);
+        return rc;
     }
     set_ok();
     return BPT_OK;

@@ -57,11 +57,14 @@ __global__ __launch_bounds__(kScanBlock) void tile_sums(const uint32_t* counts, 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// One workgroup: exclusive scan of the tile sums, total into *total and offsets[n].
+// One workgroup: exclusive scan of the tile sums, starting at *base (0 when
+// null), total into *total and offsets[n].  `base` may be `total` itself.
 __global__ __launch_bounds__(kScanBlock) void scan_tiles(unsigned long long* part, uint64_t ntiles, uint64_t n,
-                                                         unsigned long long* offsets, unsigned long long* total) {
+                                                         unsigned long long* offsets, unsigned long long* total,
+                                                         const unsigned long long* base) {
     __shared__ unsigned long long tmp[kScanBlock / kWave];
-    unsigned long long carry = 0;
+    unsigned long long carry = base ? *base : 0ull;
+    __syncthreads();  // every thread has read *base before thread 0 may overwrite it
     for (uint64_t b = 0; b < ntiles; b += kScanBlock) {
         const uint64_t i = b + threadIdx.x;
         const unsigned long long x = i < ntiles ? part[i] : 0ull;
@@ -126,14 +129,16 @@ size_t finalize_scratch_bytes(uint64_t n_samples) {
 hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
                            uint64_t n_samples, unsigned long long* offsets, uint32_t* vertices,
                            unsigned long long capacity, unsigned long long* total, const unsigned int* err,
-                           void* scratch, size_t scratch_bytes, hipStream_t stream) {
+                           void* scratch, size_t scratch_bytes, hipStream_t stream,
+                           const unsigned long long* base) {
     const uint64_t ntiles = (n_samples + kTile - 1) / kTile;
     if (scratch_bytes < finalize_scratch_bytes(n_samples)) return hipErrorInvalidValue;
     unsigned long long* part = static_cast<unsigned long long*>(scratch);
     if (ntiles > 0) {
         hipLaunchKernelGGL(tile_sums, dim3((unsigned)ntiles), dim3(kScanBlock), 0, stream, counts, n_samples, part);
     }
-    hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanBlock), 0, stream, part, ntiles, n_samples, offsets, total);
+    hipLaunchKernelGGL(scan_tiles, dim3(1), dim3(kScanBlock), 0, stream, part, ntiles, n_samples, offsets, total,
+                       base);
     if (ntiles > 0) {
         hipLaunchKernelGGL(tile_offsets, dim3((unsigned)ntiles), dim3(kScanBlock), 0, stream, counts, n_samples,
                            part, offsets);

@@ -159,11 +159,14 @@ hipError_t launch_fused(const FusedArgs& a, int nw, int block, int grid, bool he
 hipError_t launch_unfused(const UnfusedArgs& a, int grid, hipStream_t stream);
 // CSR assembly of one job's sets: offsets by a scan of `counts`, then a
 // gather from the pool (skipped when the total exceeds `capacity` or the pool
-// overflowed).  The total goes to offsets[n_samples] and *total.
+// overflowed).  The total goes to offsets[n_samples] and *total.  With `base`
+// (device memory, may equal `total`) the offsets start at *base instead of 0:
+// consecutive sample ranges of one request appended into one CSR.
 hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
                            uint64_t n_samples, unsigned long long* offsets, uint32_t* vertices,
                            unsigned long long capacity, unsigned long long* total, const unsigned int* err,
-                           void* scratch, size_t scratch_bytes, hipStream_t stream);
+                           void* scratch, size_t scratch_bytes, hipStream_t stream,
+                           const unsigned long long* base = nullptr);
 size_t finalize_scratch_bytes(uint64_t n_samples);
 
 constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
