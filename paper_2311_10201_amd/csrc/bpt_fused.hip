@@ -115,6 +115,7 @@ struct FusedShared {
     uint32_t dq_e[BS / kWave][kDiscQueue];
     uint16_t dq_c[BS / kWave][kDiscQueue];
     uint32_t dq_len[BS / kWave];
+    uint32_t next_item;  // work items of the current chunk handed out to wavefronts so far
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
@@ -560,21 +561,35 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
 
     // pass 1: per-colour member counts of this wave's chunk range; lane l
     // keeps the count of colour k*64 + l.
+    // kB chunks per round (one-word masks), their list entries and masks loaded together
+    constexpr uint32_t kB = NW == 1 ? 4 : 1;
     uint32_t mycnt[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) mycnt[k] = 0;
-    for (uint32_t ch = c_begin; ch < c_end; ++ch) {
-        const uint32_t idx = ch * kWave + lane;
-        const uint32_t u = idx < T ? list[idx] : kNone;
+    for (uint32_t ch = c_begin; ch < c_end; ch += kB) {
+        uint32_t u[kB];
+        unsigned long long mk[kB][NW];
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const unsigned long long mk = (u != kNone) ? load_coherent64(&b.visited[(size_t)u * NW + k]) : 0ull;
-            unsigned long long present = wave_or64(mk);
-            while (present) {
-                const int bpos = __ffsll((long long)present) - 1;
-                present &= present - 1;
-                const unsigned long long bal = __ballot((mk >> bpos) & 1ull);
-                if ((int)lane == bpos) mycnt[k] += (uint32_t)__popcll(bal);
+        for (uint32_t r = 0; r < kB; ++r) {
+            const uint32_t idx = (ch + r) * kWave + lane;
+            u[r] = (ch + r < c_end && idx < T) ? list[idx] : kNone;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < kB; ++r)
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+                mk[r][k] = (u[r] != kNone) ? load_coherent64(&b.visited[(size_t)u[r] * NW + k]) : 0ull;
+#pragma unroll
+        for (uint32_t r = 0; r < kB; ++r) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                unsigned long long present = wave_or64(mk[r][k]);
+                while (present) {
+                    const int bpos = __ffsll((long long)present) - 1;
+                    present &= present - 1;
+                    const unsigned long long bal = __ballot((mk[r][k] >> bpos) & 1ull);
+                    if ((int)lane == bpos) mycnt[k] += (uint32_t)__popcll(bal);
+                }
             }
         }
     }
@@ -597,26 +612,38 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
 #pragma unroll
     for (int k = 0; k < NW; ++k) run[k] = s.base + s.coff[k * 64 + lane] + s.u.ex.wprefix[wid][k * 64 + lane];
     const unsigned long long lt = lanemask_lt();
-    for (uint32_t ch = c_begin; ch < c_end; ++ch) {
-        const uint32_t idx = ch * kWave + lane;
-        const uint32_t u = idx < T ? list[idx] : kNone;
+    for (uint32_t ch = c_begin; ch < c_end; ch += kB) {
+        uint32_t u[kB];
+        unsigned long long mk[kB][NW];
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const unsigned long long mk = (u != kNone) ? load_coherent64(&b.visited[(size_t)u * NW + k]) : 0ull;
-            unsigned long long present = wave_or64(mk);
-            while (present) {
-                const int bpos = __ffsll((long long)present) - 1;
-                present &= present - 1;
-                const bool mine = (mk >> bpos) & 1ull;
-                const unsigned long long bal = __ballot(mine);
-                const unsigned long long pos0 = bcast64(run[k], bpos);
-                if (mine && write_ok) pool[pos0 + (unsigned long long)__popcll(bal & lt)] = u;
-                if ((int)lane == bpos) run[k] += (unsigned long long)__popcll(bal);
-            }
+        for (uint32_t r = 0; r < kB; ++r) {
+            const uint32_t idx = (ch + r) * kWave + lane;
+            u[r] = (ch + r < c_end && idx < T) ? list[idx] : kNone;
         }
-        if (u != kNone) {
 #pragma unroll
-            for (int k = 0; k < NW; ++k) store_coherent64(&b.visited[(size_t)u * NW + k], 0ull);
+        for (uint32_t r = 0; r < kB; ++r)
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+                mk[r][k] = (u[r] != kNone) ? load_coherent64(&b.visited[(size_t)u[r] * NW + k]) : 0ull;
+#pragma unroll
+        for (uint32_t r = 0; r < kB; ++r) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                unsigned long long present = wave_or64(mk[r][k]);
+                while (present) {
+                    const int bpos = __ffsll((long long)present) - 1;
+                    present &= present - 1;
+                    const bool mine = (mk[r][k] >> bpos) & 1ull;
+                    const unsigned long long bal = __ballot(mine);
+                    const unsigned long long pos0 = bcast64(run[k], bpos);
+                    if (mine && write_ok) pool[pos0 + (unsigned long long)__popcll(bal & lt)] = u[r];
+                    if ((int)lane == bpos) run[k] += (unsigned long long)__popcll(bal);
+                }
+            }
+            if (u[r] != kNone) {
+#pragma unroll
+                for (int k = 0; k < NW; ++k) store_coherent64(&b.visited[(size_t)u[r] * NW + k], 0ull);
+            }
         }
     }
 }
@@ -969,6 +996,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     s.u.st.scan[tid * kEPT + j] = excl;
                     excl += my_items[j];
                 }
+                if (tid == 0) s.next_item = 0;
                 __syncthreads();
 
                 const bool heavy = help_ok && total >= kHelpMinUnits * BS;
@@ -1068,10 +1096,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     }
                     drain_queue<NW, BS, true>(g, b, s, ct_own, nxt, qnext, tag, base_tag, true);
                 } else {
-                    for (uint32_t t0 = 0; t0 < total; t0 += BS) {
-                        if (t0 + tid < total)
-                            run_item<NW, BS, false>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered, t0 + tid,
-                                                    npos, nxt, qnext, tag, base_tag, th_philox, th_live);
+                    // wavefronts claim 64 consecutive items at a time, so a wavefront slowed
+                    // by its SIMD's other work takes fewer of them
+                    for (;;) {
+                        uint32_t t0 = 0;
+                        if (lane_id() == 0) t0 = atomicAdd(&s.next_item, (uint32_t)kWave);
+                        t0 = uni32(__shfl(t0, 0, kWave));
+                        if (t0 >= total) break;
+                        if (t0 + lane_id() < total)
+                            run_item<NW, BS, false>(g, seed, a.gather_mode, b, s, ct_own, s0, first, ordered,
+                                                    t0 + lane_id(), npos, nxt, qnext, tag, base_tag, th_philox,
+                                                    th_live);
                         drain_queue<NW, BS, false>(g, b, s, ct_own, nxt, qnext, tag, base_tag, false);
                     }
                     drain_queue<NW, BS, false>(g, b, s, ct_own, nxt, qnext, tag, base_tag, true);
@@ -1151,19 +1186,32 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
             const size_t words = bitmap_words(n);
             const size_t per_t = (words + BS - 1) / BS;
             const size_t w0 = min(words, (size_t)tid * per_t), w1 = min(words, w0 + per_t);
+            // eight words per round, their loads issued together
+            constexpr uint32_t kR = 8;
             uint32_t ones = 0;
-            for (size_t w = w0; w < w1; ++w) ones += (uint32_t)__popcll(load_coherent64(&b.tbits[w]));
+            for (size_t w = w0; w < w1; w += kR) {
+                unsigned long long x[kR];
+#pragma unroll
+                for (uint32_t r = 0; r < kR; ++r) x[r] = w + r < w1 ? load_coherent64(&b.tbits[w + r]) : 0ull;
+#pragma unroll
+                for (uint32_t r = 0; r < kR; ++r) ones += (uint32_t)__popcll(x[r]);
+            }
             uint32_t all;
             uint32_t pos = block_excl_scan<BS>(ones, s.scan_tmp[scan_buf], &all);
-            for (size_t w = w0; w < w1; ++w) {
-                unsigned long long x = load_coherent64(&b.tbits[w]);
-                if (!x) continue;
-                store_coherent64(&b.tbits[w], 0ull);
-                while (x) {
-                    const uint32_t bpos = (uint32_t)(__ffsll((long long)x) - 1);
-                    x &= x - 1;
-                    if (pos < n) b.touched[pos] = (uint32_t)(w * 64 + bpos);
-                    ++pos;
+            for (size_t w = w0; w < w1; w += kR) {
+                unsigned long long x[kR];
+#pragma unroll
+                for (uint32_t r = 0; r < kR; ++r) x[r] = w + r < w1 ? load_coherent64(&b.tbits[w + r]) : 0ull;
+#pragma unroll
+                for (uint32_t r = 0; r < kR; ++r) {
+                    if (!x[r]) continue;
+                    store_coherent64(&b.tbits[w + r], 0ull);
+                    while (x[r]) {
+                        const uint32_t bpos = (uint32_t)(__ffsll((long long)x[r]) - 1);
+                        x[r] &= x[r] - 1;
+                        if (pos < n) b.touched[pos] = (uint32_t)((w + r) * 64 + bpos);
+                        ++pos;
+                    }
                 }
             }
             __syncthreads();
