@@ -668,6 +668,7 @@ def main() -> int:
                     help="timed steps of each comparison variant (unfused, other colour counts)")
     ap.add_argument("--colors", type=int, default=0, help="0: pick the fastest listed colour count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the library's launch-shape tuner")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (known bytes, for counter scaling)")
@@ -727,6 +728,15 @@ def main() -> int:
     g = bpt.bpt_create_graph(n, src, dst, prob)
     log(f"graph n={n} m={m} layout={bpt.bpt_graph_info(g)[2]} built in {time.perf_counter() - t0:.2f}s")
     stream = torch.cuda.current_stream()
+    tuner = None
+    if not args.no_tune and not args.only:
+        # the library's launch-shape tuner on its capped trial (8 .. 1024 colours, then the colour
+        # schedule); untimed, reported beside the full-size variants
+        t0 = time.perf_counter()
+        tc = bpt.bpt_tune_colors(g, S, seed)
+        tuner = {"colors": tc, "seconds": time.perf_counter() - t0,
+                 "note": "bpt_tune_colors on its trial of min(S, 4 x 64 x resident workgroups) samples"}
+        log(f"tuner: {tc} colours in {tuner['seconds']:.1f}s")
     off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
     cap = max(1 << 20, 48 * S)
     vert = torch.empty(cap, dtype=torch.int32, device="cuda")
@@ -891,6 +901,7 @@ def main() -> int:
         "fused_vs_unfused": (value / others["unfused"]["samples_per_s"]) if "unfused" in others else None,
         "host_api": host_api,
         "variants": others,
+        "tuner": tuner,
         "roofline": roofline,
     }
 

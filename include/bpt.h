@@ -336,6 +336,42 @@ int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uin
                      uint64_t capacity, int64_t* d_result);
 
 /* ------------------------------------------------------------------------
+ * Multi-job plans: bpt_sample_rrr_jobs (many graphs and sample ranges in one
+ * persistent launch per mask width, paper Section 4.1) as a fixed sequence of
+ * kernels that can be captured into one hipGraph and replayed.
+ *
+ * bpt_jobs_plan_create reserves, once, everything the n_jobs jobs need: a
+ * traversal workspace per mask width sized for its largest graph, per-sample
+ * arrays, member pools (pool_capacity entries in all, split over the launches
+ * in proportion to the jobs' capacities; 0 takes the graphs' running
+ * estimates of the set sizes) and the device
+ * job tables.  Each job's graph, n_samples, colors_per_batch (0: as for the
+ * job alone), d_offsets, d_vertices and capacity are fixed here, and its
+ * buffers must stay valid while the plan is used; first_sample and seed are
+ * taken from the job as defaults.  Returns NULL on error: BPT_EINVAL (as
+ * bpt_sample_rrr_jobs), BPT_ENOMEM, BPT_EDEVICE.  Free with bpt_free(), after
+ * the graphs' last use by the plan and before the graphs.
+ *
+ * bpt_jobs_plan_enqueue enqueues one sampling of every job on `stream` and
+ * returns at once; like bpt_plan_enqueue it allocates nothing, launches only
+ * kernels and never waits, so it may be captured.
+ *   d_params   NULL, or device memory with 2 * n_jobs uint64: {first_sample,
+ *              seed} of job i at [2i], [2i+1], read when the stream reaches the
+ *              call: one captured graph then samples whatever ranges and seeds
+ *              the caller writes there before each replay.
+ *   d_results  device (or mapped pinned host) memory with 2 * n_jobs int64:
+ *              {status, members} of job i at [2i], [2i+1], as bpt_plan_enqueue
+ *              reports them (BPT_ERANGE with the pool entries needed when a
+ *              launch's pool overflowed).
+ * Each job's sets equal bpt_sample_rrr_device's for its graph, range, seed
+ * and colours.  Calls on one plan must not overlap in time.  Returns BPT_OK
+ * when enqueued; BPT_EINVAL (not a multi-job plan, d_results NULL) or
+ * BPT_EDEVICE.
+ * ---------------------------------------------------------------------- */
+bpt_plan* bpt_jobs_plan_create(const bpt_job* jobs, uint32_t n_jobs, uint64_t pool_capacity);
+int bpt_jobs_plan_enqueue(bpt_plan* p, const uint64_t* d_params, void* stream, int64_t* d_results);
+
+/* ------------------------------------------------------------------------
  * bpt_max_cover - influence-maximization seeds from sampled RRR sets (paper
  * Section 2: with reverse influence sampling, choosing k seeds is a maximum
  * k-coverage over the sets; the greedy choice gives a 1 - 1/e approximation).
@@ -461,14 +497,19 @@ int bpt_graph_set_vertex_order(bpt_graph* g, const uint32_t* rank);
 uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples);
 
 /* ------------------------------------------------------------------------
- * bpt_tune_colors - colour-count autotuner.  Times the fused traversal of
+ * bpt_tune_colors - launch-shape autotuner.  Times the fused traversal of
  * sample ids 0 .. min(n_samples, 4 x 64 x resident workgroups) - 1 under
- * `seed` at 8, 16, ..., 256 colours per batch (two runs each, HIP events,
- * traversal plus CSR assembly) and remembers the fastest for this graph and
- * jobs of the same power-of-two size range as n_samples: later calls with
- * colors_per_batch = 0 (and bpt_default_colors) use it.  Which width is
- * fastest depends on the graph and probabilities (dense sharing favours wide
- * batches, small jobs narrow ones); the sets never do.
+ * `seed` (two runs each, HIP events, traversal plus CSR assembly) at 8, 16,
+ * ..., 1024 colours per batch, then, at the fastest width, with the colour
+ * schedule of the expansion forced to per-coin discovery and to per-edge
+ * gathering of live colours instead of the kernel's per-wavefront choice
+ * (kept when 3% faster).  It remembers the result for this graph and jobs of
+ * the same power-of-two size range as n_samples: later calls with
+ * colors_per_batch = 0 (and bpt_default_colors) take the colour count, and
+ * calls at that colour count take the schedule.  Which shape is fastest
+ * depends on the graph and probabilities (dense sharing favours wide batches
+ * and gathering, small jobs narrow ones); the sets never do.  Trials of wide
+ * masks on large graphs allocate and free tens of GB of traversal slots.
  *
  * Returns the chosen colour count, or 0 on error (bpt_last_status():
  * BPT_EINVAL for a bad handle or n_samples outside [1, 2^34), or the errors

@@ -22,7 +22,8 @@ __all__ = [
     "BptError", "Counters", "Graph", "Job", "RRRResult", "Request", "Server", "BPT_REQ_SAMPLE", "BPT_REQ_SEEDS",
     "bpt_create_graph", "bpt_sample_rrr", "bpt_free", "bpt_sample_rrr_device", "bpt_sample_rrr_jobs",
     "bpt_sample_rrr_noalloc",
-    "bpt_max_cover", "Plan", "bpt_plan_create", "bpt_plan_enqueue",
+    "bpt_max_cover", "Plan", "bpt_plan_create", "bpt_plan_enqueue", "bpt_jobs_plan_create",
+    "bpt_jobs_plan_enqueue",
     "bpt_graph_info", "bpt_graph_set_vertex_order",
     "bpt_graph_release_cache",
     "bpt_default_colors", "bpt_tune_colors", "bpt_thr32", "bpt_coin_word", "bpt_start_vertex", "bpt_version",
@@ -53,7 +54,7 @@ EXPORTED_SYMBOLS = (
     "bpt_coin_word", "bpt_start_vertex", "bpt_version", "bpt_sample_rrr_jobs", "bpt_max_cover",
     "bpt_server_create", "bpt_server_submit", "bpt_server_wait", "bpt_server_now", "bpt_server_stats",
     "bpt_server_destroy", "bpt_graph_set_vertex_order", "bpt_plan_create", "bpt_plan_enqueue",
-    "bpt_sample_rrr_noalloc",
+    "bpt_sample_rrr_noalloc", "bpt_jobs_plan_create", "bpt_jobs_plan_enqueue",
 )
 
 
@@ -225,6 +226,8 @@ def load_library():
         "bpt_sample_rrr_jobs": (i32, [ctypes.POINTER(_Job), u32, vp, ctypes.POINTER(_Counters)]),
         "bpt_plan_create": (vp, [vp, u64, u32, u64]),
         "bpt_plan_enqueue": (i32, [vp, u64, u64, u64, vp, vp, vp, vp, u64, vp]),
+        "bpt_jobs_plan_create": (vp, [ctypes.POINTER(_Job), u32, u64]),
+        "bpt_jobs_plan_enqueue": (i32, [vp, vp, vp, vp]),
         "bpt_max_cover": (i32, [vp, vp, u64, u32, u32, vp, vp, vp]),
         "bpt_server_create": (vp, [u64, u32]),
         "bpt_server_submit": (i32, [vp, ctypes.POINTER(_Request)]),
@@ -447,6 +450,30 @@ def bpt_plan_enqueue(plan: Plan, first_sample: int, n_samples: int, seed: int, d
     st = load_library().bpt_plan_enqueue(plan.handle, first_sample, n_samples, seed, _addr(d_params),
                                          _stream(stream), _addr(d_offsets), _addr(d_vertices), capacity,
                                          _addr(d_result))
+    if st != BPT_OK:
+        _raise_last()
+
+
+def bpt_jobs_plan_create(jobs, pool_capacity: int = 0) -> Plan:
+    """A capturable plan for a fixed list of Jobs (their graphs, sample counts,
+    colours and device buffers are fixed; ranges and seeds can change per call)."""
+    lib = load_library()
+    arr = (_Job * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        arr[i] = _Job(j.graph.handle, j.first_sample, j.n_samples, j.seed, j.colors_per_batch, 0,
+                      _addr(j.d_offsets), _addr(j.d_vertices), j.capacity, 0, 0, 0)
+    h = lib.bpt_jobs_plan_create(arr, len(jobs), pool_capacity)
+    if not h:
+        _raise_last()
+    plan = Plan(h, jobs[0].graph, 0)
+    plan.jobs = list(jobs)  # the buffers must outlive the plan
+    return plan
+
+
+def bpt_jobs_plan_enqueue(plan: Plan, d_params, stream, d_results) -> None:
+    """Enqueues one sampling of every job of a multi-job plan (kernels only;
+    capturable); {status, members} of job i land in d_results[2i], [2i+1]."""
+    st = load_library().bpt_jobs_plan_enqueue(plan.handle, _addr(d_params), _stream(stream), _addr(d_results))
     if st != BPT_OK:
         _raise_last()
 

@@ -64,6 +64,13 @@ void dev_free(void* p) {
     if (p) (void)hipFree(p);
 }
 
+// What bpt_tune_colors measured fastest for one job-size range of a graph:
+// colours per batch and the colour schedule of the expansion (GatherMode).
+struct TunedShape {
+    uint32_t colors = 0;
+    uint32_t gather = kGatherAuto;
+};
+
 // One set of traversal state + output staging; a call holds one exclusively.
 struct Workspace {
     int nw = 0;  // colour words per mask (fused), 0 = unfused
@@ -142,7 +149,7 @@ struct bpt_graph {
     uint32_t* d_thr_edge;
     std::mutex mu;
     std::vector<bpt::Workspace*> idle;
-    uint32_t tuned[64] = {};  // colours measured fastest for jobs of 2^i .. 2^(i+1)-1 samples (0: none)
+    bpt::TunedShape tuned[64];  // measured fastest for jobs of 2^i .. 2^(i+1)-1 samples (colors 0: none)
     double mean_members = 0;  // running mean set size of this graph's calls (0: none yet), sizes pools
     uint32_t* d_rank = nullptr;  // vertex order for sorted starts (null: vertex ids)
 };
@@ -150,13 +157,35 @@ struct bpt_graph {
 // A reusable, capturable sampling setup: a private workspace with its pool and
 // per-sample arrays, and a one-entry device job table that the setup kernel
 // fills at run time.
+namespace bpt {
+namespace {
+// One launch of a multi-job plan: the jobs whose batches use `nw` mask words.
+// Table entries 0 .. n_fused-1 (jobs with samples) are in the fused launch;
+// every entry gets a CSR assembly and a result.
+struct PlanGroup {
+    int nw = 1;
+    bpt_graph* owner = nullptr;       // the group's graph with the most vertices
+    Workspace* ws = nullptr;          // its d_jobs / d_totals hold the group's table
+    std::vector<bpt_job> jobs;        // as given at creation, table order
+    std::vector<uint64_t> out_base;   // position of each job's first sample in counts / where
+    uint32_t n_fused = 0;
+    uint64_t n_batches = 0;
+    uint32_t* d_ids = nullptr;        // the caller's index of each table entry
+    unsigned long long* d_caps = nullptr;
+};
+}  // namespace
+}  // namespace bpt
+
 struct bpt_plan {
     uint32_t magic;
-    bpt_graph* graph;
+    bpt_graph* graph;  // single-job plan; null for a multi-job plan
     bpt::Workspace* ws;
     bpt::FusedJob* d_job;
     uint64_t max_samples;
     uint32_t colors;
+    std::vector<bpt::PlanGroup> groups;  // multi-job plan
+    uint32_t n_jobs = 0;
+    int device = 0;
 };
 
 struct bpt_rrr {
@@ -196,13 +225,19 @@ int fused_block(int nw) {
 // Workgroups of `bs` threads resident per CU (1024 threads per CU).
 uint64_t fused_per_cu(int bs) { return (uint64_t)(1024 / bs); }
 
-// Colour schedule of the fused expansion: chosen by the kernel, or forced
-// (BPT_GATHER=never|always, for tests and tuning; the sets are the same).
-uint32_t gather_mode() {
+// Colour schedule of the fused expansion: chosen by the kernel per
+// wavefront, measured by the tuner, or forced (BPT_GATHER=never|always|auto,
+// for tests; the sets are the same).  -1: not forced.
+int gather_forced() {
     const char* v = getenv("BPT_GATHER");
     if (v && !strcmp(v, "never")) return kGatherNever;
     if (v && !strcmp(v, "always")) return kGatherAlways;
-    return kGatherAuto;
+    if (v && !strcmp(v, "auto")) return kGatherAuto;
+    return -1;
+}
+uint32_t gather_mode() {
+    const int f = gather_forced();
+    return f >= 0 ? (uint32_t)f : kGatherAuto;
 }
 
 void fused_launch_shape(const bpt_graph* g, int nw, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
@@ -505,6 +540,8 @@ void ensure_jobs(Workspace* ws, uint32_t n_jobs) {
     ws->jobs_cap = cap;
 }
 
+uint32_t gather_for(bpt_graph* g, uint64_t n_samples, uint32_t colors);
+
 struct CallResult {
     uint64_t total = 0;
     bpt_counters counters{};
@@ -522,7 +559,7 @@ void release_or_discard(bpt_graph* g, Workspace* ws, const CallResult& r) {
 // BPT_ERANGE may reuse the sets the failed call left in the workspace.
 int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32_t colors, uint64_t seed,
                  uint32_t flags, hipStream_t stream, unsigned long long* d_offsets, uint32_t* d_vertices,
-                 uint64_t capacity, bool own_output, bool retry_ok, CallResult* res) {
+                 uint64_t capacity, bool own_output, bool retry_ok, CallResult* res, int gather = -1) {
     const bool unfused = (flags & BPT_FLAG_UNFUSED) != 0;
     const bool sorted = (flags & BPT_FLAG_SORTED_STARTS) != 0;
     const bool reuse = retry_ok && ws->have_last && ws->last_first == first && ws->last_samples == S &&
@@ -603,7 +640,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.out = out;
             a.ctl = ws->ctl;
             a.n_batches = (S + colors - 1) / colors;
-            a.gather_mode = gather_mode();
+            a.gather_mode = gather >= 0 ? (uint32_t)gather : gather_for(g, S, colors);
             fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, help_wanted(g), stream));
         } else {
@@ -801,10 +838,20 @@ int size_bucket(uint64_t n_samples) { return n_samples ? 63 - __builtin_clzll(n_
 
 uint64_t fused_resident(const bpt_graph* g) { return (uint64_t)g->cus * fused_per_cu(fused_block(1)); }
 
+// The colour schedule of a call: forced by BPT_GATHER, else the one the tuner
+// measured with these colours for this job size, else the kernel's choice.
+uint32_t gather_for(bpt_graph* g, uint64_t n_samples, uint32_t colors) {
+    const int f = gather_forced();
+    if (f >= 0) return (uint32_t)f;
+    std::lock_guard<std::mutex> lk(g->mu);
+    const TunedShape& t = g->tuned[size_bucket(n_samples)];
+    return t.colors == colors ? t.gather : kGatherAuto;
+}
+
 uint32_t choose_colors(bpt_graph* g, uint64_t n_samples) {
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        const uint32_t t = g->tuned[size_bucket(n_samples)];
+        const uint32_t t = g->tuned[size_bucket(n_samples)].colors;
         if (t) return t;
     }
     const uint64_t resident = fused_resident(g);
@@ -1231,7 +1278,7 @@ int bpt_sample_rrr_noalloc(bpt_graph* g, uint64_t first_sample, uint64_t n_sampl
             a.out.pool_cap = pool_cap;
             a.ctl = ctl;
             a.n_batches = n_batches;
-            a.gather_mode = gather_mode();
+            a.gather_mode = gather_for(gg, n_samples, colors);
             int block = 0, grid = 0;
             fused_launch_shape(gg, nw, (uint32_t)slots, n_batches, &block, &grid);
             HIP_TRY(launch_fused(a, nw, block, grid, help_wanted(gg), st));
@@ -1546,6 +1593,7 @@ bpt_plan* bpt_plan_create(bpt_graph* g, uint64_t max_samples, uint32_t colors_pe
         p = new bpt_plan();
         p->magic = kDeadMagic;  // until complete
         p->graph = gg;
+        p->device = gg->device;
         p->max_samples = max_samples;
         p->colors = colors;
         const int nw = mask_words(colors);
@@ -1582,8 +1630,8 @@ bpt_plan* bpt_plan_create(bpt_graph* g, uint64_t max_samples, uint32_t colors_pe
 
 int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uint64_t seed, const uint64_t* d_params,
                      void* stream, uint64_t* d_offsets, uint32_t* d_vertices, uint64_t capacity, int64_t* d_result) {
-    if (!p || p->magic != kPlanMagic) {
-        set_status(BPT_EINVAL, "not a bpt_plan handle");
+    if (!p || p->magic != kPlanMagic || !p->graph) {
+        set_status(BPT_EINVAL, "not a single-job bpt_plan handle");
         return BPT_EINVAL;
     }
     if (!d_offsets || !d_result || (!d_vertices && capacity > 0)) {
@@ -1618,7 +1666,7 @@ int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uin
             a.out.pool_cap = ws->pool_cap;
             a.ctl = ws->ctl;
             a.n_batches = (n_samples + p->colors - 1) / p->colors;
-            a.gather_mode = gather_mode();
+            a.gather_mode = gather_for(p->graph, p->max_samples, p->colors);
             int block = 0, grid = 0;
             fused_launch_shape(p->graph, ws->nw, ws->slots, a.n_batches, &block, &grid);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, help_wanted(p->graph), st));
@@ -1627,6 +1675,176 @@ int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uin
                                 reinterpret_cast<unsigned long long*>(d_offsets), d_vertices, capacity,
                                 &ws->ctl->total, &ws->ctl->err, ws->scratch, ws->scratch_bytes, st));
         HIP_TRY(launch_plan_report(ws->ctl, capacity, d_result, st));
+    } catch (const HipFail& f) {
+        set_status(f.status, f.msg);
+        return f.status;
+    }
+    set_ok();
+    return BPT_OK;
+}
+
+bpt_plan* bpt_jobs_plan_create(const bpt_job* jobs, uint32_t n_jobs, uint64_t pool_capacity) {
+    if (n_jobs == 0 || !jobs) {
+        set_status(BPT_EINVAL, "at least one job is required");
+        return nullptr;
+    }
+    bpt_plan* p = nullptr;
+    try {
+        std::vector<uint32_t> colors(n_jobs);
+        bpt_graph* first = nullptr;
+        for (uint32_t i = 0; i < n_jobs; ++i) {
+            const bpt_job& jb = jobs[i];
+            bpt_graph* gg = check_graph(jb.graph);
+            if (!gg) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) + ": not a bpt_graph handle");
+                return nullptr;
+            }
+            if (first && gg->device != first->device) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) + ": graphs of one plan must share a device");
+                return nullptr;
+            }
+            if (!first) first = gg;
+            if (!jb.d_offsets || (!jb.d_vertices && jb.capacity > 0) || jb.reserved || jb.reserved2) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) +
+                                           ": d_offsets required (d_vertices when capacity > 0), reserved = 0");
+                return nullptr;
+            }
+            if (jb.n_samples >= kMaxSamples || jb.first_sample >= kMaxSamples ||
+                jb.first_sample + jb.n_samples > kMaxSamples) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) + ": sample ids must stay below 2^34");
+                return nullptr;
+            }
+            colors[i] = jb.colors_per_batch ? jb.colors_per_batch : choose_colors(gg, jb.n_samples);
+            if (!valid_colors(colors[i])) {
+                set_status(BPT_EINVAL, "job " + std::to_string(i) +
+                                           ": colors_per_batch must be 0 or a power of two from 8 to 1024");
+                return nullptr;
+            }
+        }
+        HIP_TRY(hipSetDevice(first->device));
+        p = new bpt_plan();
+        p->magic = kDeadMagic;  // until complete
+        p->graph = nullptr;
+        p->ws = nullptr;
+        p->d_job = nullptr;
+        p->device = first->device;
+        p->n_jobs = n_jobs;
+        uint64_t cap_all = 0;  // pool_capacity is split over the launches by the jobs' capacities
+        for (uint32_t i = 0; i < n_jobs; ++i) cap_all += jobs[i].capacity;
+        std::vector<uint32_t> empty_jobs;  // no samples: only an empty CSR and a result, in the one-word group
+        for (uint32_t i = 0; i < n_jobs; ++i)
+            if (jobs[i].n_samples == 0) empty_jobs.push_back(i);
+        for (int w = 16; w >= 1; w >>= 1) {
+            std::vector<uint32_t> fused, empty;
+            for (uint32_t i = 0; i < n_jobs; ++i)
+                if (jobs[i].n_samples && mask_words(colors[i]) == w) fused.push_back(i);
+            if (w == 1) empty = empty_jobs;
+            if (fused.empty() && empty.empty()) continue;
+            p->groups.emplace_back();
+            PlanGroup& gr = p->groups.back();
+            gr.nw = w;
+            std::vector<uint32_t> ids = fused;
+            ids.insert(ids.end(), empty.begin(), empty.end());
+            gr.n_fused = (uint32_t)fused.size();
+            uint64_t samples = 0, est = 0, cap_group = 0;
+            std::vector<FusedJob> table(ids.size());
+            std::vector<unsigned long long> caps(ids.size());
+            for (size_t t = 0; t < ids.size(); ++t) {
+                const bpt_job& jb = jobs[ids[t]];
+                bpt_graph* gg = check_graph(jb.graph);
+                if (!gr.owner || gg->n > gr.owner->n) gr.owner = gg;
+                gr.jobs.push_back(jb);
+                gr.out_base.push_back(samples);
+                FusedJob& fj = table[t];
+                fj = FusedJob{};
+                fj.g = dev_graph(gg);
+                fj.seed = jb.seed;
+                fj.first_sample = jb.first_sample;
+                fj.n_samples = jb.n_samples;
+                fj.batch_begin = gr.n_batches;
+                fj.out_base = samples;
+                fj.colors = colors[ids[t]];
+                gr.n_batches += (jb.n_samples + fj.colors - 1) / fj.colors;
+                samples += jb.n_samples;
+                est += pool_estimate(gg, jb.n_samples);
+                caps[t] = jb.capacity;
+                cap_group += jb.capacity;
+            }
+            gr.ws = make_workspace(gr.owner, w, std::max<uint64_t>(gr.n_batches, 1));
+            ensure_sample_arrays(gr.ws, std::max<uint64_t>(samples, 1));
+            ensure_jobs(gr.ws, (uint32_t)ids.size());
+            const uint64_t pool =
+                pool_capacity ? (uint64_t)((double)pool_capacity * (double)cap_group / (double)std::max<uint64_t>(cap_all, 1)) + 1024
+                              : est;
+            ensure_pool(gr.owner, gr.ws, std::max<uint64_t>(pool, 1024));
+            gr.d_ids = dev_alloc<uint32_t>(ids.size());
+            gr.d_caps = dev_alloc<unsigned long long>(ids.size());
+            HIP_TRY(hipMemcpy(gr.ws->d_jobs, table.data(), table.size() * sizeof(FusedJob), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(gr.d_ids, ids.data(), ids.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(gr.d_caps, caps.data(), caps.size() * sizeof(unsigned long long),
+                              hipMemcpyHostToDevice));
+        }
+        HIP_TRY(hipDeviceSynchronize());
+        p->magic = kPlanMagic;
+    } catch (const HipFail& f) {
+        if (p) {
+            p->magic = kPlanMagic;
+            bpt_free(p);
+        }
+        set_status(f.status, f.msg);
+        return nullptr;
+    } catch (const std::bad_alloc&) {
+        if (p) {
+            p->magic = kPlanMagic;
+            bpt_free(p);
+        }
+        set_status(BPT_ENOMEM, "host allocation failed");
+        return nullptr;
+    }
+    set_ok();
+    return p;
+}
+
+int bpt_jobs_plan_enqueue(bpt_plan* p, const uint64_t* d_params, void* stream, int64_t* d_results) {
+    if (!p || p->magic != kPlanMagic || p->graph || !d_results) {
+        set_status(BPT_EINVAL, "a multi-job bpt_plan handle and d_results are required");
+        return BPT_EINVAL;
+    }
+    try {
+        HIP_TRY(hipSetDevice(p->device));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (PlanGroup& gr : p->groups) {
+            Workspace* ws = gr.ws;
+            HIP_TRY(launch_plan_setup_jobs(ws->d_jobs, gr.n_fused, d_params, gr.d_ids, kMaxSamples, ws->ctl, st));
+            if (gr.n_fused > 0) {
+                FusedArgs a = {};
+                a.jobs = ws->d_jobs;
+                a.n_jobs = gr.n_fused;
+                a.n_max = gr.owner->n;
+                a.ws = ws->fs;
+                a.out.counts = ws->counts;
+                a.out.where = ws->where;
+                a.out.pool = ws->pool;
+                a.out.pool_cap = ws->pool_cap;
+                a.ctl = ws->ctl;
+                a.n_batches = gr.n_batches;
+                a.gather_mode = gather_mode();
+                int block = 0, grid = 0;
+                fused_launch_shape(gr.owner, gr.nw, ws->slots, gr.n_batches, &block, &grid);
+                bool help = false;
+                for (uint32_t t = 0; t < gr.n_fused; ++t) help = help || help_wanted(check_graph(gr.jobs[t].graph));
+                HIP_TRY(launch_fused(a, gr.nw, block, grid, help, st));
+            }
+            for (size_t t = 0; t < gr.jobs.size(); ++t) {
+                const bpt_job& jb = gr.jobs[t];
+                HIP_TRY(launch_finalize(ws->counts + gr.out_base[t], ws->where + gr.out_base[t], ws->pool,
+                                        jb.n_samples, reinterpret_cast<unsigned long long*>(jb.d_offsets),
+                                        jb.d_vertices, jb.capacity, ws->d_totals + t, &ws->ctl->err, ws->scratch,
+                                        ws->scratch_bytes, st));
+            }
+            HIP_TRY(launch_plan_report_jobs(ws->ctl, ws->d_totals, gr.d_caps, gr.d_ids, (uint32_t)gr.jobs.size(),
+                                            d_results, st));
+        }
     } catch (const HipFail& f) {
         set_status(f.status, f.msg);
         return f.status;
@@ -1657,9 +1875,14 @@ void bpt_free(void* handle) {
     } else if (magic == kPlanMagic) {
         bpt_plan* p = static_cast<bpt_plan*>(handle);
         p->magic = kDeadMagic;
-        (void)hipSetDevice(p->graph->device);
+        (void)hipSetDevice(p->device);
         delete p->ws;
         dev_free(p->d_job);
+        for (PlanGroup& gr : p->groups) {
+            delete gr.ws;
+            dev_free(gr.d_ids);
+            dev_free(gr.d_caps);
+        }
         delete p;
         set_ok();
     } else if (magic == kRrrMagic) {
@@ -1730,29 +1953,47 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
     // Jobs beyond four 64-colour batches per resident workgroup behave alike
     // per batch: the trial is capped there.
     const uint64_t S = std::min<uint64_t>(n_samples, 4 * 64 * fused_resident(gg));
-    uint32_t best = 0;
-    uint64_t best_ns = ~0ull;
     Workspace* ws = nullptr;
+    // best of two runs (the first also loads the kernel and sizes the pool), traversal + CSR assembly
+    auto trial = [&](uint32_t c, int gather, uint64_t* ns_out) -> int {
+        ws = acquire(gg, mask_words(c), (S + c - 1) / c);
+        uint64_t ns = ~0ull;
+        for (int rep = 0; rep < 2; ++rep) {
+            CallResult res;
+            const int rc = run_sampling(gg, ws, 0, S, c, seed, 0u, nullptr, nullptr, nullptr, 0, true, false, &res,
+                                        gather);
+            if (rc != BPT_OK) {
+                release_or_discard(gg, ws, res);
+                ws = nullptr;
+                return rc;  // status set by run_sampling
+            }
+            ns = std::min<uint64_t>(ns, res.counters.traversal_ns + res.counters.finalize_ns);
+        }
+        release(gg, ws);
+        ws = nullptr;
+        trim_idle(gg, -1);  // one width's slots at a time: wide masks take most of the memory
+        *ns_out = ns;
+        return BPT_OK;
+    };
+    TunedShape best;
     try {
         HIP_TRY(hipSetDevice(gg->device));
-        for (uint32_t c = 8; c <= 256; c <<= 1) {
-            ws = acquire(gg, mask_words(c), (S + c - 1) / c);
-            uint64_t ns = ~0ull;
-            for (int rep = 0; rep < 2; ++rep) {  // the first run also loads the kernel
-                CallResult res;
-                const int rc = run_sampling(gg, ws, 0, S, c, seed, 0u, nullptr, nullptr, nullptr, 0, true, false,
-                                              &res);
-                if (rc != BPT_OK) {
-                    release_or_discard(gg, ws, res);
-                    return 0;  // status set by run_sampling
-                }
-                ns = std::min<uint64_t>(ns, res.counters.traversal_ns + res.counters.finalize_ns);
-            }
-            release(gg, ws);
-            ws = nullptr;
+        uint64_t best_ns = ~0ull;
+        for (uint32_t c = 8; c <= 1024; c <<= 1) {  // colours per batch, under the kernel's own schedule choice
+            uint64_t ns = 0;
+            if (trial(c, kGatherAuto, &ns) != BPT_OK) return 0;
             if (ns < best_ns) {
                 best_ns = ns;
-                best = c;
+                best.colors = c;
+            }
+        }
+        // then the colour schedule at that width: forced either way, kept if 3% faster
+        for (uint32_t mode : {(uint32_t)kGatherNever, (uint32_t)kGatherAlways}) {
+            uint64_t ns = 0;
+            if (trial(best.colors, (int)mode, &ns) != BPT_OK) return 0;
+            if (ns * 100 < best_ns * 97) {
+                best_ns = ns;
+                best.gather = mode;
             }
         }
     } catch (const HipFail& f) {
@@ -1768,9 +2009,8 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
         std::lock_guard<std::mutex> lk(gg->mu);
         gg->tuned[size_bucket(n_samples)] = best;
     }
-    trim_idle(gg, mask_words(best));  // the trial workspaces of the other widths are not kept
     set_ok();
-    return best;
+    return best.colors;
 }
 
 uint32_t bpt_thr32(float p) { return threshold_of(p); }

@@ -184,6 +184,13 @@ hipError_t launch_sort_by_start(uint32_t n, uint64_t seed, uint64_t first, uint6
 hipError_t launch_plan_setup(FusedJob* job, const uint64_t* params, uint64_t first, uint64_t seed,
                              uint64_t n_samples, uint64_t max_ids, Control* ctl, hipStream_t stream);
 hipError_t launch_plan_report(const Control* ctl, unsigned long long capacity, int64_t* result, hipStream_t stream);
+// Multi-job plans: the same around a job table (ids[i]: the caller's index of
+// table entry i, which selects its params and its result).
+hipError_t launch_plan_setup_jobs(FusedJob* jobs, uint32_t n_jobs, const uint64_t* params, const uint32_t* ids,
+                                  uint64_t max_ids, Control* ctl, hipStream_t stream);
+hipError_t launch_plan_report_jobs(const Control* ctl, const unsigned long long* totals,
+                                   const unsigned long long* capacities, const uint32_t* ids, uint32_t n_jobs,
+                                   int64_t* result, hipStream_t stream);
 
 // Allocation-free calls (bpt_noalloc.hip): a fixed scratch array per device,
 // resolved to its device address once per device (the device must be

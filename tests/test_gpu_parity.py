@@ -255,7 +255,7 @@ def test_tuned_colors_are_remembered(er_case):
     before = bpt.bpt_default_colors(other, 3000)
     announce("tune colours S=3000")
     c = bpt.bpt_tune_colors(g, 3000, 5)
-    assert c in (8, 16, 32, 64, 128, 256)
+    assert c in (8, 16, 32, 64, 128, 256, 512, 1024)
     assert bpt.bpt_default_colors(g, 3000) == c
     assert bpt.bpt_default_colors(g, 2048) == c and bpt.bpt_default_colors(g, 4095) == c
     assert bpt.bpt_default_colors(other, 3000) == before
