@@ -525,7 +525,8 @@ def bench_serve(args, w) -> int:
     for i in range(N):
         gi = int(rng.integers(len(graphs)))
         S = int(round(math.exp(rng.uniform(math.log(w["samples_lo"]), math.log(w["samples_hi"])))))
-        kind = bpt.BPT_REQ_SEEDS if rng.random() < w["seeds_fraction"] else bpt.BPT_REQ_SAMPLE
+        frac = w["seeds_fraction"] if args.seeds_fraction < 0 else args.seeds_fraction
+        kind = bpt.BPT_REQ_SEEDS if rng.random() < frac else bpt.BPT_REQ_SAMPLE
         reqs.append(dict(gi=gi, S=S, kind=kind, seed=10_000 + i, first=0))
     # set-size means per graph (for caller buffers of sample requests)
     for gr in graphs:
@@ -551,6 +552,33 @@ def bench_serve(args, w) -> int:
         if r["kind"] == bpt.BPT_REQ_SEEDS:
             seeds = bpt.bpt_max_cover(off, vert, r["S"], g["n"], w["k"], stream)[0]
         return off, vert, total, seeds
+
+    # a single large request alone: through the server (chunked launches on two
+    # streams) and as one library call, to show what chunking costs
+    chunk_check = None
+    big = dict(gi=4, S=1_000_000, kind=bpt.BPT_REQ_SAMPLE, seed=7, first=0)
+    alone(big)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    alone(big)
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t
+    srv0 = bpt.Server()
+    off0, vert0, cap0 = buffers(big)
+    for rep in range(2):
+        q0 = bpt.Request(big["kind"], graphs[big["gi"]]["g"], 0, big["S"], big["seed"], d_offsets=off0,
+                         d_vertices=vert0, capacity=cap0, tag=rep)
+        t = time.perf_counter()
+        srv0.submit(q0)
+        q0 = srv0.wait(60.0)
+        t_srv = time.perf_counter() - t
+    launches0 = srv0.stats()["launches"] / 2
+    srv0.close()
+    chunk_check = {"samples": big["S"], "graph": f"R-MAT {w['scales'][big['gi']]} WC", "alone_ms": t_alone * 1e3,
+                   "server_ms": t_srv * 1e3, "server_launches": launches0}
+    log(f"serve: one 1M-sample request alone {t_alone * 1e3:.1f} ms, through the server {t_srv * 1e3:.1f} ms "
+        f"({launches0:.0f} launches)")
+    del off0, vert0
 
     # one at a time: service time of each request alone
     for r in reqs[:4]:
@@ -579,25 +607,50 @@ def bench_serve(args, w) -> int:
     samples = sum(r["S"] for r in reqs)
     log(f"serve: one at a time {serial_s:.1f}s of service, capacity {capacity:.1f} req/s; arrivals at {rate:.1f}/s")
 
-    # the server, same arrival times
+    # the server, same arrival times; every request and its output buffers are
+    # made before the clock starts, so the submitting thread only waits and submits.
+    # The graphs' cached workspaces from the one-at-a-time pass are released first
+    # (the server sizes its own traversal slots from the memory left).
+    for gr in graphs:
+        bpt.bpt_graph_release_cache(gr["g"])
+    torch.cuda.empty_cache()
     srv = bpt.Server()
     done = {}
+    prepared = []
+    for i, r in enumerate(reqs):
+        g = graphs[r["gi"]]["g"]
+        if r["kind"] == bpt.BPT_REQ_SAMPLE:
+            off, vert, cap = buffers(r)
+            q = bpt.Request(r["kind"], g, r["first"], r["S"], r["seed"], d_offsets=off, d_vertices=vert,
+                            capacity=cap, tag=i)
+        else:
+            q = bpt.Request(r["kind"], g, r["first"], r["S"], r["seed"], k=w["k"], tag=i)
+        prepared.append(q)
+    torch.cuda.synchronize()
+    # warm-up before the clock, as at a service's start: the largest graph's
+    # request on both lanes sizes their traversal workspaces and pools
+    t = time.perf_counter()
+    gbig = max(range(len(graphs)), key=lambda i: graphs[i]["n"])
+    warm_req = dict(gi=gbig, S=w["samples_hi"], kind=bpt.BPT_REQ_SAMPLE, seed=7, first=0)
+    off_w, vert_w, cap_w = buffers(warm_req)
+    for rep in range(2):
+        srv.submit(bpt.Request(bpt.BPT_REQ_SAMPLE, graphs[gbig]["g"], 0, w["samples_hi"], 7, d_offsets=off_w,
+                               d_vertices=vert_w, capacity=cap_w, tag=-1))
+        assert srv.wait(120.0) is not None
+        log(f"serve: warm-up request {rep} done after {time.perf_counter() - t:.2f} s")
+    del off_w, vert_w
+    warm = srv.stats()
+    lag = np.zeros(N)
 
     def submitter():
         base = srv.now()
-        for i, r in enumerate(reqs):
+        for i, q in enumerate(prepared):
             delay = base + arrivals[i] - srv.now()
             if delay > 0:
                 time.sleep(delay)
-            g = graphs[r["gi"]]["g"]
-            if r["kind"] == bpt.BPT_REQ_SAMPLE:
-                off, vert, cap = buffers(r)
-                q = bpt.Request(r["kind"], g, r["first"], r["S"], r["seed"], d_offsets=off, d_vertices=vert,
-                                capacity=cap, tag=i)
-            else:
-                q = bpt.Request(r["kind"], g, r["first"], r["S"], r["seed"], k=w["k"], tag=i)
             q.arrival = base + arrivals[i]
             srv.submit(q)
+            lag[i] = q.t_submit - q.arrival
 
     th = threading.Thread(target=submitter)
     t_run = time.perf_counter()
@@ -608,13 +661,13 @@ def bench_serve(args, w) -> int:
             log("serve: no completion for 30 s")
             break
         done[q.tag] = q
-        if q.kind == bpt.BPT_REQ_SAMPLE and q.tag % w["check_every"]:
-            q.d_offsets = q.d_vertices = None  # free the buffers of requests that are not checked
         if len(done) % 250 == 0:
             log(f"serve: {len(done)} of {N} completed")
     th.join()
     run_s = time.perf_counter() - t_run
     info = srv.stats()
+    for key in ("launches", "served", "busy_s", "sample_s", "cover_s", "alloc_s", "resampled"):
+        info[key] -= warm[key]
     launches, served = info["launches"], info["served"]
     srv.close()
     ok = len(done) == N and all(q.status == bpt.BPT_OK for q in done.values())
@@ -635,7 +688,26 @@ def bench_serve(args, w) -> int:
             same = q.total == total and np.array_equal(q.seeds[:w["k"]], seeds)
 
     def pct(x, p):
-        return float(np.percentile(x, p)) * 1e3
+        return float(np.percentile(x, p)) * 1e3 if len(x) else None
+
+    breakdown = None
+    if ok:
+        kinds = np.array([r["kind"] for r in reqs])
+        sizes = np.array([r["S"] for r in reqs])
+        start = np.array([done[i].t_start - done[i].arrival for i in range(N)])
+        third = np.percentile(sizes, [100 / 3, 200 / 3])
+        groups = {"sample_requests": kinds == bpt.BPT_REQ_SAMPLE, "seed_requests": kinds == bpt.BPT_REQ_SEEDS,
+                  "smallest_third": sizes <= third[0], "largest_third": sizes > third[1]}
+        breakdown = {name: {"server_p50_ms": pct(lat_srv[m], 50), "server_p99_ms": pct(lat_srv[m], 99),
+                            "one_at_a_time_p50_ms": pct(lat_serial[m], 50),
+                            "one_at_a_time_p99_ms": pct(lat_serial[m], 99)} for name, m in groups.items()}
+        breakdown["server_wait_to_first_launch_p50_ms"] = pct(start, 50)
+        breakdown["server_wait_to_first_launch_p99_ms"] = pct(start, 99)
+        early = arrivals < 1.0
+        breakdown["server_wait_to_first_launch_first_second_p99_ms"] = pct(start[early], 99)
+        breakdown["server_wait_to_first_launch_after_first_second_p99_ms"] = pct(start[~early], 99)
+        breakdown["submit_lag_p50_ms"] = pct(lag, 50)
+        breakdown["submit_lag_p99_ms"] = pct(lag, 99)
 
     result = {
         "metric": "RRR requests served (sets or k = 50 influence-maximization seeds): samples/s and p50/p99 "
@@ -648,9 +720,12 @@ def bench_serve(args, w) -> int:
                    "k": w["k"], "arrival_rate_per_s": rate, "load_vs_one_at_a_time": load},
         "server": {"p50_ms": pct(lat_srv, 50), "p99_ms": pct(lat_srv, 99), "launches": launches,
                    "requests_per_launch": served / max(1, launches), "wall_s": run_s,
-                   "worker_s": {k: info[k] for k in ("busy_s", "sample_s", "cover_s", "alloc_s")}},
+                   "worker_s": {k: info[k] for k in ("busy_s", "sample_s", "cover_s", "alloc_s")},
+                   "resampled": info["resampled"], "batch_us_estimate": info["batch_s"] * 1e6},
         "one_at_a_time": {"p50_ms": pct(lat_serial, 50), "p99_ms": pct(lat_serial, 99), "service_s": serial_s,
                           "capacity_req_per_s": capacity, "samples_per_s_at_capacity": samples / serial_s},
+        "chunking_check": chunk_check,
+        "latency_breakdown": breakdown,
         "parity": (f"server results == the same requests alone on {len(range(0, N, w['check_every']))} checked "
                    "requests" if same else "MISMATCH or failed requests"),
     }
@@ -674,6 +749,8 @@ def main() -> int:
                     help="first run one plain 1 GiB device-to-device copy (known bytes, for counter scaling)")
     ap.add_argument("--only", default="", help="time only this variant (fused64, fused256, unfused, ...)")
     ap.add_argument("--requests", type=int, default=0, help="serve8: number of requests (default 2000)")
+    ap.add_argument("--seeds-fraction", type=float, default=-1.0,
+                    help="serve8: share of influence-maximization requests (default 0.25)")
     ap.add_argument("--load", type=float, default=0.0,
                     help="serve8: arrival rate as a multiple of one-at-a-time capacity (default 0.8)")
     ap.add_argument("--tune", action="store_true",

@@ -391,7 +391,10 @@ int bpt_jobs_plan_enqueue(bpt_plan* p, const uint64_t* d_params, void* stream, i
  *   gains       host, k entries (out): sets newly covered by each seed, so
  *               n * (sum of gains) / n_sets estimates the seeds' influence.
  *
- * Device scratch of about 5n + n_sets bytes is allocated per call.  Returns
+ * Each step visits only the sets that hold the chosen vertex, through an
+ * inverted index (vertex -> sets) built first by a counting sort.  Device
+ * scratch of about 21n + n_sets + 4 x (members) bytes is allocated per call.
+ * Returns
  * BPT_OK; BPT_EINVAL for bad arguments, offsets that are not a CSR of
  * d_vertices, or a member >= n (checked on the device before any set is
  * touched); BPT_ENOMEM; BPT_EDEVICE.
@@ -406,18 +409,20 @@ int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_
  * and a second thread for seed selection.  Requests submitted from any thread
  * are queued; the worker admits them in arrival order while their estimated
  * memory (the sets' expected size from a running per-graph mean, plus
- * per-sample arrays) fits the budget, always one when nothing runs.  The GPU
- * is fed a pipeline of bounded persistent launches on two streams: each
- * launch takes the next batches of every admitted request, an equal share
- * each, about two batches per resident workgroup in all (at most
- * max_jobs_per_launch requests), and the next launch is enqueued while the
- * current one drains.  A request that arrives while others are on the GPU
- * therefore joins the next launch and shares it with them.  Each chunk's CSR
+ * per-sample arrays) fits the budget, always one when nothing runs, and at
+ * most 64 at a time.  The GPU is fed a pipeline of bounded persistent
+ * launches on two streams: each launch takes about four batches per
+ * resident workgroup (at most max_jobs_per_launch requests), given out in
+ * order of deadline, the submission time plus four times the request's
+ * estimated service time; the next launch is enqueued while the current one
+ * drains.
+ * A request that arrives while others are on the GPU therefore joins the
+ * next launch and shares it with them.  Each chunk's CSR
  * is appended to its request's output in sample order; a request completes
  * when its last chunk has, and seed requests then run bpt_max_cover on the
  * second thread while sampling continues.  Every request gets exactly the
- * result it would get alone.  Colour counts are bpt_default_colors capped
- * at 64.
+ * result it would get alone.  Every request is sampled at 64 colours per
+ * batch (the sets do not depend on it).
  * ---------------------------------------------------------------------- */
 typedef struct bpt_server bpt_server;
 
@@ -450,7 +455,11 @@ typedef struct bpt_request {
 /* memory_budget: bytes of admitted work at a time (0: 8 GiB);
  * max_jobs_per_launch: requests sharing one launch at most, 0 for 256.
  * Device memory: two traversal workspaces sized for the largest graph seen
- * (about 36 bytes per vertex per resident workgroup each) and their pools.
+ * (about 36 bytes per vertex per resident workgroup each, from at most 60%
+ * of the free memory) and their pools.  A workspace is made, or remade
+ * larger, by the first launch that needs it: on a 4M-vertex graph that takes
+ * seconds, and requests queued meanwhile wait, so a service submits one
+ * request on its largest graph at start.
  * NULL on failure. */
 bpt_server* bpt_server_create(uint64_t memory_budget, uint32_t max_jobs_per_launch);
 /* Queues r; r must stay valid until bpt_server_wait returns it.  BPT_EINVAL
@@ -468,6 +477,11 @@ typedef struct bpt_server_info {
     double sample_s;   /* ... of which with a launch in flight               */
     double cover_s;    /* seed-selection time (second thread)                */
     double alloc_s;    /* time getting seed requests' set buffers            */
+    uint64_t resampled;/* requests sampled again alone (their launch's pool
+                          overflowed, or a seed request's sets outgrew the
+                          server's buffer)                                   */
+    double batch_s;    /* current estimate of GPU seconds per 64-sample batch
+                          (orders requests by deadline)                      */
 } bpt_server_info;
 int bpt_server_stats(bpt_server* s, bpt_server_info* out);
 /* Serves what is queued, then stops the worker and frees the server. */

@@ -98,7 +98,8 @@ class _Request(ctypes.Structure):
 
 class _ServerInfo(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("served", ctypes.c_uint64), ("busy_s", ctypes.c_double),
-                ("sample_s", ctypes.c_double), ("cover_s", ctypes.c_double), ("alloc_s", ctypes.c_double)]
+                ("sample_s", ctypes.c_double), ("cover_s", ctypes.c_double), ("alloc_s", ctypes.c_double),
+                ("resampled", ctypes.c_uint64), ("batch_s", ctypes.c_double)]
 
 
 BPT_REQ_SAMPLE = 0

@@ -307,9 +307,12 @@ size_t carve_fused_slots(char* base, uint32_t n, int nw, uint32_t slots, FusedSl
 
 size_t unfused_slot_bytes(uint32_t n) { return bitmap_words(n) * 8 + (size_t)n * 4; }
 
-size_t memory_budget() {
+// Device memory a new workspace may take: a third of what is free (at most
+// 96 GB), or `fraction` of it (at most 160 GB) when given.
+size_t memory_budget(double fraction = 0.0) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return (size_t)8 << 30;
+    if (fraction > 0.0) return std::min((size_t)((double)free_b * fraction), (size_t)160 << 30);
     return std::min(free_b / 3, (size_t)96 << 30);
 }
 
@@ -330,12 +333,12 @@ uint64_t slots_wanted(const bpt_graph* g, int nw, uint64_t units) {
     return std::min(want, cap);
 }
 
-Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
+Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units, double budget_fraction = 0.0) {
     Workspace* ws = new Workspace();
     ws->nw = nw;
     try {
         const uint32_t n = g->n;
-        const size_t budget = memory_budget();
+        const size_t budget = memory_budget(budget_fraction);
         char* p;
         if (nw > 0) {
             const size_t per = fused_slot_bytes(n, nw) + 1024;
@@ -873,6 +876,11 @@ struct Lane {
     uint32_t ws_n = 0;          // vertices per slot of ws
     uint64_t pool_floor = 0;    // pool entries the last overflow showed to be needed
     bool pending = false;       // a launch was enqueued and not yet waited for
+    FinSeg* h_seg = nullptr;    // CSR assembly table of the launch (pinned host, device)
+    FinSeg* d_seg = nullptr;
+    uint32_t seg_cap = 0;
+    void* fin_scratch = nullptr;  // partial sums of the segmented assembly
+    size_t fin_bytes = 0;
 };
 
 Lane* lane_create(int device, std::string* why) {
@@ -896,6 +904,9 @@ void lane_destroy(Lane* l) {
     if (!l) return;
     if (l->stream) (void)hipStreamSynchronize(l->stream);
     delete l->ws;
+    if (l->h_seg) (void)hipHostFree(l->h_seg);
+    dev_free(l->d_seg);
+    dev_free(l->fin_scratch);
     if (l->done) (void)hipEventDestroy(l->done);
     if (l->stream) (void)hipStreamDestroy(l->stream);
     delete l;
@@ -930,16 +941,37 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
         if (!l->ws || l->ws_n < owner->n) {  // slots for the largest graph so far, as many as the GPU keeps resident
             delete l->ws;
             l->ws = nullptr;
-            l->ws = make_workspace(owner, 1, ~0ull >> 1);
+            // a lane's launches need every resident workgroup: up to 60% of the free memory
+            l->ws = make_workspace(owner, 1, ~0ull >> 1, 0.6);
             l->ws_n = owner->n;
         }
         Workspace* ws = l->ws;
         ensure_sample_arrays(ws, total_samples);
         ensure_jobs(ws, n);
         if (ws->pool_cap < std::max(est, l->pool_floor)) ensure_pool(owner, ws, std::max(est, l->pool_floor) * 2);
-        uint64_t b = 0, base = 0;
+        if (l->seg_cap < n) {
+            if (l->h_seg) (void)hipHostFree(l->h_seg);
+            dev_free(l->d_seg);
+            l->h_seg = nullptr;
+            l->d_seg = nullptr;
+            l->seg_cap = 0;
+            const uint32_t cap = std::max<uint32_t>(n, 64);
+            HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&l->h_seg), cap * sizeof(FinSeg), hipHostMallocDefault));
+            l->d_seg = dev_alloc<FinSeg>(cap);
+            l->seg_cap = cap;
+        }
+        uint64_t b = 0, base = 0, tiles = 0;
         for (uint32_t i = 0; i < n; ++i) {
             const LaneChunk& c = chunks[i];
+            FinSeg& sg = l->h_seg[i];
+            sg.count_base = base;
+            sg.n = c.n_samples;
+            sg.tile_base = tiles;
+            sg.offsets = c.d_offsets;
+            sg.vertices = c.d_vertices;
+            sg.capacity = c.capacity;
+            sg.total = c.d_total;
+            tiles += finalize_tiles(c.n_samples);
             FusedJob& fj = ws->h_jobs[i];
             fj = FusedJob{};
             fj.g = dev_graph(c.graph);
@@ -952,8 +984,17 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
             b += (c.n_samples + c.colors - 1) / c.colors;
             base += c.n_samples;
         }
+        if (l->fin_bytes < tiles * sizeof(unsigned long long)) {
+            dev_free(l->fin_scratch);
+            l->fin_scratch = nullptr;
+            l->fin_bytes = 0;
+            const size_t bytes = std::max<size_t>(tiles * 2 * sizeof(unsigned long long), 4096);
+            l->fin_scratch = dev_alloc<char>(bytes);
+            l->fin_bytes = bytes;
+        }
         HIP_TRY(hipMemsetAsync(ws->ctl, 0, sizeof(Control), l->stream));
         HIP_TRY(hipMemcpyAsync(ws->d_jobs, ws->h_jobs, n * sizeof(FusedJob), hipMemcpyHostToDevice, l->stream));
+        HIP_TRY(hipMemcpyAsync(l->d_seg, l->h_seg, n * sizeof(FinSeg), hipMemcpyHostToDevice, l->stream));
         FusedArgs a = {};
         a.jobs = ws->d_jobs;
         a.n_jobs = n;
@@ -972,13 +1013,8 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
         // launch (on the other lane) takes their place while this one drains
         HIP_TRY(launch_fused(a, 1, block, grid, false, l->stream));
         if (after) HIP_TRY(hipStreamWaitEvent(l->stream, after, 0));
-        for (uint32_t i = 0; i < n; ++i) {
-            const LaneChunk& c = chunks[i];
-            const uint64_t ob = ws->h_jobs[i].out_base;
-            HIP_TRY(launch_finalize(ws->counts + ob, ws->where + ob, ws->pool, c.n_samples, c.d_offsets,
-                                    c.d_vertices, c.capacity, c.d_total, &ws->ctl->err, ws->scratch,
-                                    ws->scratch_bytes, l->stream, c.d_total));
-        }
+        HIP_TRY(launch_finalize_segments(ws->counts, ws->where, ws->pool, total_samples, l->d_seg, n, tiles,
+                                         &ws->ctl->err, l->fin_scratch, l->fin_bytes, l->stream));
         HIP_TRY(hipMemcpyAsync(ws->ctl_host, ws->ctl, sizeof(Control), hipMemcpyDeviceToHost, l->stream));
         HIP_TRY(hipEventRecord(l->done, l->stream));
         l->pending = true;
@@ -1016,10 +1052,13 @@ int lane_wait(Lane* l, bool* overflow, std::string* why) {
     return BPT_OK;
 }
 
-size_t max_cover_scratch(uint64_t n_sets, uint32_t n, uint32_t k) { return max_cover_scratch_bytes(n_sets, n, k); }
+size_t max_cover_scratch(uint64_t n_sets, uint32_t n, uint32_t k, uint64_t total) {
+    return max_cover_scratch_bytes(n_sets, n, k, total);
+}
 
 int max_cover_run(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
-                  hipStream_t st, uint32_t* seeds, uint64_t* gains, void* scratch, std::string* why) {
+                  hipStream_t st, uint32_t* seeds, uint64_t* gains, void* scratch, size_t scratch_bytes,
+                  std::string* why) {
     if (!d_offsets || !seeds || !gains || n == 0 || k > n || n_sets >= (1ull << 32)) {
         *why = "d_offsets, seeds and gains are required; 1 <= n, k <= n, n_sets < 2^32";
         return BPT_EINVAL;
@@ -1031,6 +1070,10 @@ int max_cover_run(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_
         HIP_TRY(hipStreamSynchronize(st));
         if (total > 0 && !d_vertices) {
             *why = "d_vertices is required when the sets have members";
+            return BPT_EINVAL;
+        }
+        if (scratch_bytes < max_cover_scratch_bytes(n_sets, n, k, total)) {
+            *why = "coverage scratch too small for " + std::to_string(total) + " members";
             return BPT_EINVAL;
         }
         uint32_t* seeds_dev = nullptr;
@@ -1489,14 +1532,21 @@ int bpt_max_cover(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_
         set_ok();
         return BPT_OK;
     }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint64_t total = 0;
+    if (hipMemcpyAsync(&total, d_offsets + n_sets, sizeof(uint64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_status(BPT_EDEVICE, "reading the sets' member count");
+        return BPT_EDEVICE;
+    }
     void* scratch = nullptr;
-    if (hipMalloc(&scratch, max_cover_scratch_bytes(n_sets, n, k)) != hipSuccess) {
+    const size_t bytes = max_cover_scratch_bytes(n_sets, n, k, total);
+    if (hipMalloc(&scratch, bytes) != hipSuccess) {
         set_status(BPT_ENOMEM, "device scratch of the coverage greedy");
         return BPT_ENOMEM;
     }
     std::string why;
-    const int rc = max_cover_run(d_offsets, d_vertices, n_sets, n, k, static_cast<hipStream_t>(stream), seeds, gains,
-                                 scratch, &why);
+    const int rc = max_cover_run(d_offsets, d_vertices, n_sets, n, k, st, seeds, gains, scratch, bytes, &why);
     (void)hipFree(scratch);
     if (rc != BPT_OK) {
         set_status(rc, why);

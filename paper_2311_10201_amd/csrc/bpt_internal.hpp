@@ -169,6 +169,25 @@ hipError_t launch_finalize(const uint32_t* counts, const unsigned long long* whe
                            const unsigned long long* base = nullptr);
 size_t finalize_scratch_bytes(uint64_t n_samples);
 
+// Many jobs' CSR assembly in four kernels (segment j: counts/where entries
+// [count_base, count_base + n), partial sums [tile_base, tile_base +
+// finalize_tiles(n))), each appended at its own running total (which it
+// then advances) into its own offsets / vertices.  Segments by ascending
+// count_base and tile_base; the table lives in device memory.
+struct FinSeg {
+    uint64_t count_base;
+    uint64_t n;
+    uint64_t tile_base;
+    unsigned long long* offsets;  // n + 1 entries written
+    uint32_t* vertices;
+    unsigned long long capacity;
+    unsigned long long* total;    // running member count: base in, total out
+};
+uint64_t finalize_tiles(uint64_t n_samples);
+hipError_t launch_finalize_segments(const uint32_t* counts, const unsigned long long* where, const uint32_t* pool,
+                                    uint64_t n_all, const FinSeg* d_seg, uint32_t nseg, uint64_t ntiles,
+                                    const unsigned int* err, void* scratch, size_t scratch_bytes, hipStream_t stream);
+
 constexpr int kUnfusedBlock = 256;  // threads per unfused workgroup (4 waves, one sample each)
 
 // Sorted starts (bpt_order.hip): order[i] = indices 0 .. S-1 of samples
@@ -202,7 +221,7 @@ hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t stream);
 // Greedy maximum coverage (bpt_cover.hip).  Error bits of its device flag.
 constexpr unsigned int kCoverBadOffsets = 1u;  // offsets not non-decreasing or past the member count
 constexpr unsigned int kCoverBadVertex = 2u;   // a member id >= n
-size_t max_cover_scratch_bytes(uint64_t n_sets, uint32_t n, uint32_t k);
+size_t max_cover_scratch_bytes(uint64_t n_sets, uint32_t n, uint32_t k, uint64_t total);
 hipError_t launch_max_cover(const uint64_t* offsets, const uint32_t* vertices, uint64_t n_sets, uint64_t total,
                             uint32_t n, uint32_t k, void* scratch, uint32_t** seeds_dev,
                             unsigned long long** gains_dev, unsigned int** bad_dev, hipStream_t stream);

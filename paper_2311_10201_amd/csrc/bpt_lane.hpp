@@ -50,9 +50,11 @@ bool lane_finished(Lane* l);
 int lane_wait(Lane* l, bool* overflow, std::string* why);
 
 // Greedy maximum coverage (as bpt_max_cover) with caller-provided device
-// scratch of max_cover_scratch_bytes(n_sets, n, k) bytes.
+// scratch of max_cover_scratch(n_sets, n, k, total) bytes, where total is the
+// sets' member count.
 int max_cover_run(const uint64_t* d_offsets, const uint32_t* d_vertices, uint64_t n_sets, uint32_t n, uint32_t k,
-                  hipStream_t stream, uint32_t* seeds, uint64_t* gains, void* scratch, std::string* why);
-size_t max_cover_scratch(uint64_t n_sets, uint32_t n, uint32_t k);
+                  hipStream_t stream, uint32_t* seeds, uint64_t* gains, void* scratch, size_t scratch_bytes,
+                  std::string* why);
+size_t max_cover_scratch(uint64_t n_sets, uint32_t n, uint32_t k, uint64_t total);
 
 }  // namespace bpt

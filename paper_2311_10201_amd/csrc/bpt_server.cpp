@@ -6,10 +6,15 @@
 // launches on two lanes (bpt_lane.hpp):
 //  * admission: queued requests enter the running set in arrival order while
 //    their estimated memory fits the budget (always one when nothing runs);
-//  * a launch takes the next batches of every running request, an equal
-//    share each, up to a fixed number of batches per launch, so a request
-//    that arrives while others are on the GPU joins the very next launch and
-//    shares it with them instead of waiting for them to finish;
+//  * a launch takes up to a fixed number of batches (four per resident
+//    workgroup), filled in order of deadline: submission time plus four
+//    times the request's estimated service time (its batches at the measured
+//    time per batch).  A request that arrives while others are on the GPU
+//    joins the very next launch, a small one finishes within it instead of
+//    waiting behind large ones, and a large one moves ahead of newer small
+//    ones as its deadline approaches;
+//  * at most 64 requests run at a time; all chunks of a launch share one
+//    CSR assembly (four kernels per launch, whatever the number of chunks);
 //  * the next launch is enqueued on the other lane while the current one
 //    drains, so the GPU fills with the new launch's batches during the old
 //    one's tail; each chunk's CSR assembly appends to its request's output,
@@ -20,6 +25,7 @@
 // Each request's sets are the ones it would get alone: they depend only on
 // (graph, sample range, seed), never on chunking or on the other requests.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -40,6 +46,16 @@ namespace {
 constexpr uint32_t kServerMagic = 0x42505353u;  // "BPSS"
 constexpr uint32_t kLanes = 2;
 constexpr uint32_t kTotalsSlots = 1u << 16;  // running member counts of admitted requests (device)
+constexpr size_t kMaxRunning = 64;           // admitted requests at a time
+constexpr double kSlowdown = 4.0;            // deadline: submission + this many times the estimated service
+
+double env_double(const char* name, double dflt) {
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    char* end = nullptr;
+    const double x = strtod(v, &end);
+    return (end && *end == 0 && x >= 0) ? x : dflt;
+}
 
 // Device buffers of seed requests' sets and of the coverage greedy, kept for
 // reuse: freeing device memory would wait for every launch in flight.
@@ -94,6 +110,8 @@ struct Live {
 struct InFlight {
     uint32_t lane;
     std::vector<Live*> owners;  // one entry per chunk
+    uint64_t batches = 0;
+    double issued = 0.0;        // server clock when enqueued
 };
 
 }  // namespace
@@ -102,7 +120,9 @@ struct bpt_server {
     uint32_t magic = kServerMagic;
     uint64_t budget = 0;
     uint32_t max_jobs = 0;
-    uint64_t launch_batches = 1024;  // batches per launch: two per workgroup the fused kernel keeps resident
+    uint64_t launch_batches = 2048;  // batches per launch: four per workgroup the fused kernel keeps resident
+    double batch_s = 2e-6;           // running estimate of the GPU time per batch (deadlines)
+    uint64_t resampled = 0;          // requests sampled again alone after a pool overflow
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_cover;
@@ -213,10 +233,11 @@ void cover_main(bpt_server* sv) {
         uint32_t n = 0;
         int st = bpt_graph_info(r->graph, &n, nullptr, nullptr);
         if (st == BPT_OK) {
-            void* scratch = sv->buffers.get(bpt::max_cover_scratch(r->n_samples, n, r->k));
+            const size_t bytes = bpt::max_cover_scratch(r->n_samples, n, r->k, r->total);
+            void* scratch = sv->buffers.get(bytes);
             std::string why;
             st = scratch ? bpt::max_cover_run(lv->d_offsets, lv->d_vertices, r->n_samples, n, r->k, stream, r->seeds,
-                                              r->gains, scratch, &why)
+                                              r->gains, scratch, bytes, &why)
                          : BPT_ENOMEM;
             sv->buffers.put(scratch);
         }
@@ -243,6 +264,10 @@ void complete(bpt_server* sv, Live* lv, hipStream_t stream) {
     if (st == BPT_OK) {
         note_mean(sv, r->graph, r->n_samples, total);
         if (r->kind == BPT_REQ_SEEDS && (lv->broken || total > lv->capacity)) {
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                ++sv->resampled;
+            }
             if (!alloc_owned(sv, lv, total + total / 16 + 1024)) st = BPT_ENOMEM;
             else {
                 uint64_t t2 = 0;
@@ -250,6 +275,10 @@ void complete(bpt_server* sv, Live* lv, hipStream_t stream) {
                 total = t2;
             }
         } else if (lv->broken) {
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                ++sv->resampled;
+            }
             uint64_t t2 = 0;
             st = resample_alone(sv, lv, stream, &t2);
             total = t2;
@@ -278,7 +307,8 @@ void worker_main(bpt_server* sv) {
     for (uint32_t i = 0; i < kLanes; ++i) lanes[i] = bpt::lane_create(sv->device, &why);
     std::vector<Live*> running;        // admitted, with batches not yet launched or chunks in flight
     std::deque<InFlight> inflight;     // launches in issue order
-    uint32_t next_lane = 0, rr = 0;
+    uint32_t next_lane = 0;
+    double last_fin = 0.0;             // when the last waited-for launch finished
     for (;;) {
         // 1. admission
         std::vector<uint32_t> lv_slots;
@@ -295,7 +325,7 @@ void worker_main(bpt_server* sv) {
                 sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
                 if (sv->pending.empty()) continue;
             }
-            while (!sv->pending.empty() && !sv->free_slots.empty()) {
+            while (!sv->pending.empty() && !sv->free_slots.empty() && running.size() + admitted.size() < kMaxRunning) {
                 bpt_request* r = sv->pending.front();
                 lk.unlock();
                 const uint64_t b = estimate_bytes(sv, r);
@@ -316,8 +346,10 @@ void worker_main(bpt_server* sv) {
             lv->r = r;
             lv->bytes = admitted[ai].second;
             lv->slot = lv_slots[ai];
-            const uint32_t c = bpt_default_colors(r->graph, r->n_samples);
-            lv->colors = std::min<uint32_t>(c ? c : 64, 64);  // lanes run one-word masks
+            // 64 colours (one mask word, what the lanes run): alone, a small request would
+            // take fewer colours to give every workgroup a batch, but here other requests
+            // fill the launch, and wider batches mean fewer batches for the same samples
+            lv->colors = 64;
             lv->n_batches = (r->n_samples + lv->colors - 1) / lv->colors;
             if (r->kind == BPT_REQ_SEEDS) {
                 const uint64_t cap = (uint64_t)((double)r->n_samples * mean_of(sv, r->graph) * 1.25) + 4096;
@@ -364,15 +396,37 @@ void worker_main(bpt_server* sv) {
             if (lv->next_batch < lv->n_batches) want.push_back(lv);
         bpt::Lane* lane = lanes[next_lane];
         if (!want.empty() && lane && inflight.size() < kLanes && bpt::lane_finished(lane)) {
-            const uint64_t share = std::max<uint64_t>(1, (sv->launch_batches + want.size() - 1) / want.size());
+            // Earliest deadline first: a request's deadline is its submission time plus
+            // kSlowdown times its estimated service time (its batches at the measured
+            // time per batch), so small requests go ahead of large ones, and a large one
+            // moves ahead of newer small ones as its deadline approaches.
+            std::vector<std::pair<Live*, uint64_t>> plan;
             uint64_t room = sv->launch_batches;
+            {
+                std::vector<Live*> order(want.begin(), want.end());
+                double tb;
+                {
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    tb = sv->batch_s;
+                }
+                std::stable_sort(order.begin(), order.end(), [tb](const Live* x, const Live* y) {
+                    return x->r->t_submit + kSlowdown * tb * (double)x->n_batches <
+                           y->r->t_submit + kSlowdown * tb * (double)y->n_batches;
+                });
+                for (Live* lv : order) {
+                    if (room == 0 || plan.size() >= sv->max_jobs) break;
+                    const uint64_t t = std::min(room, lv->n_batches - lv->next_batch);
+                    plan.emplace_back(lv, t);
+                    room -= t;
+                }
+            }
             std::vector<bpt::LaneChunk> chunks;
             InFlight fl;
             fl.lane = next_lane;
-            const size_t W = want.size();
-            for (size_t k = 0; k < W && room > 0 && chunks.size() < sv->max_jobs; ++k) {
-                Live* lv = want[(rr + k) % W];
-                const uint64_t take = std::min({share, room, lv->n_batches - lv->next_batch});
+            for (auto& pt : plan) {
+                Live* lv = pt.first;
+                const uint64_t take = pt.second;
+                if (take == 0) continue;
                 bpt_request* r = lv->r;
                 const uint64_t s0 = lv->next_batch * lv->colors;
                 const uint64_t ns = std::min<uint64_t>(take * lv->colors, r->n_samples - s0);
@@ -389,14 +443,14 @@ void worker_main(bpt_server* sv) {
                 chunks.push_back(c);
                 fl.owners.push_back(lv);
                 lv->next_batch += take;
+                fl.batches += take;
                 ++lv->open_chunks;
-                room -= take;
                 if (!lv->started) {
                     lv->started = true;
                     r->t_start = sv->now();
                 }
             }
-            rr = (uint32_t)((rr + 1) % std::max<size_t>(W, 1));
+            fl.issued = sv->now();
             hipEvent_t after = inflight.empty() ? nullptr : bpt::lane_done(lanes[inflight.back().lane]);
             const int rc = bpt::lane_launch(lane, chunks.data(), (uint32_t)chunks.size(), after, &why);
             if (rc != BPT_OK) {  // nothing of it ran: its requests fail
@@ -424,23 +478,32 @@ void worker_main(bpt_server* sv) {
             continue;  // admit and launch again before waiting
         }
 
-        // 3. the oldest launch: wait for it once both lanes are busy or nothing
-        // else can go; otherwise poll it and look for arrivals
+        // 3. the oldest launch: with both lanes busy, wait for it; with a lane free,
+        // poll it and look for arrivals, which go to the free lane at once
         if (inflight.empty()) continue;
         InFlight& fl = inflight.front();
         bpt::Lane* fl_lane = lanes[fl.lane];
-        const bool must_wait = inflight.size() >= kLanes || want.empty();
-        if (!bpt::lane_finished(fl_lane)) {
+        if (inflight.size() < kLanes && !bpt::lane_finished(fl_lane)) {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (!must_wait || sv->pending.empty()) {
-                if (sv->cv_work.wait_for(lk, std::chrono::microseconds(50),
-                                         [&] { return !sv->pending.empty() && !sv->free_slots.empty(); }))
-                    continue;
-                if (!bpt::lane_finished(fl_lane)) continue;
-            }
+            if (sv->cv_work.wait_for(lk, std::chrono::microseconds(50), [&] {
+                    return !sv->pending.empty() && !sv->free_slots.empty() && running.size() < kMaxRunning;
+                }))
+                continue;
+            if (!bpt::lane_finished(fl_lane)) continue;
         }
         bool overflow = false;
         const int rc = bpt::lane_wait(fl_lane, &overflow, &why);
+        const double t_fin = sv->now();
+        if (2 * fl.batches >= sv->launch_batches) {
+            // GPU time per batch from a well-filled launch, counted from when the one
+            // before it finished (the two overlap).  Small launches are left out: their
+            // fixed cost would make every batch look slow and push large requests'
+            // deadlines far out.
+            const double per = (t_fin - std::max(fl.issued, last_fin)) / (double)fl.batches;
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->batch_s = 0.8 * sv->batch_s + 0.2 * per;
+        }
+        last_fin = t_fin;
         for (Live* lv : fl.owners) {
             --lv->open_chunks;
             if (overflow || rc != BPT_OK) lv->broken = true;
@@ -484,7 +547,9 @@ bpt_server* bpt_server_create(uint64_t memory_budget, uint32_t max_jobs_per_laun
         delete sv;
         return nullptr;
     }
-    sv->launch_batches = (uint64_t)std::max(cus, 1) * 4;  // two batches per resident 512-thread workgroup
+    // four batches per resident 512-thread workgroup (BPT_SERVE_LAUNCH_BATCHES overrides it)
+    sv->launch_batches = (uint64_t)env_double("BPT_SERVE_LAUNCH_BATCHES", (double)std::max(cus, 1) * 8);
+    if (sv->launch_batches == 0) sv->launch_batches = 1;
     sv->free_slots.reserve(kTotalsSlots);
     for (uint32_t i = kTotalsSlots; i > 0; --i) sv->free_slots.push_back(i - 1);
     sv->worker = std::thread(worker_main, sv);
@@ -541,6 +606,8 @@ int bpt_server_stats(bpt_server* s, bpt_server_info* out) {
     out->sample_s = sv->t_sample + (sv->sampling_since >= 0 ? t - sv->sampling_since : 0.0);
     out->cover_s = sv->t_cover;
     out->alloc_s = sv->t_alloc;
+    out->resampled = sv->resampled;
+    out->batch_s = sv->batch_s;
     return BPT_OK;
 }
 
