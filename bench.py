@@ -53,13 +53,14 @@ WORKLOADS = {
 }
 
 # ALU roofline of one Philox4x32-10 block on gfx950: per round two
-# v_mul_hi_u32, two v_mul_lo_u32 and two three-way xors (one v_bitop3_b32
-# each), so 40 multiplies + 20 logic instructions per block, plus ~8
-# compare/select for the four coins, all at the full vector issue rate (a
-# Philox-only kernel reaches 96% of this figure), against 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz.
+# v_mad_u64_u32 (each gives both halves of a 32x32 product) and two three-way
+# xors (one v_bitop3_b32 each), all at the full vector issue rate.  In the
+# first round only counter word 0 (the quad) differs between the quads of one
+# sample, so that round costs one multiply and one xor per block: 2 + 9 x 4 =
+# 38 for the rounds, plus ~8 compare/select for the four coins, against
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-SLOTS_PER_BLOCK = 40 + 20 + 8
+SLOTS_PER_BLOCK = 38 + 8
 PEAK_PHILOX_BLOCKS = LANE_SLOTS_PER_S / SLOTS_PER_BLOCK
 
 KERNEL_SOURCES = ["paper_2311_10201_amd/csrc/bpt_fused.hip", "paper_2311_10201_amd/csrc/bpt_rng.hpp",
@@ -812,7 +813,7 @@ def main() -> int:
         t0 = time.perf_counter()
         tc = bpt.bpt_tune_colors(g, S, seed)
         tuner = {"colors": tc, "seconds": time.perf_counter() - t0,
-                 "note": "bpt_tune_colors on its trial of min(S, 4 x 64 x resident workgroups) samples"}
+                 "note": "bpt_tune_colors on its trial of min(S, 16 x 64 x resident workgroups) samples"}
         log(f"tuner: {tc} colours in {tuner['seconds']:.1f}s")
     off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
     cap = max(1 << 20, 48 * S)
@@ -926,6 +927,17 @@ def main() -> int:
 
     achieved = blocks / trav_s
     traffic = measured_traffic(args.workload, colors, cnt.workgroup_size)
+    # algorithmic bytes of the launch from the per-unit figures (W = C / 8 bytes
+    # per mask): per frontier entry the row bounds (8 B), its mask (W) and the
+    # row's threshold (4 B, per-row layout; per-edge thresholds 4 B per edge
+    # access); per live coin the source id (4 B), the fetch-ors on visited and
+    # next frontier (2W) and a queue entry (4 B); per member its touched entry,
+    # its output id (4 B each) and the clearing of its visited mask (W)
+    W = colors // 8
+    layout = bpt.bpt_graph_info(g)[2]
+    thr_bytes = {0: 0, 1: 4 * cnt.frontier_entries, 2: 4 * cnt.edge_accesses}.get(layout, 0)
+    algo_bytes = (cnt.frontier_entries * (8 + W) + thr_bytes + cnt.live_coins * (8 + 2 * W) +
+                  cnt.members * (8 + W))
     # the library's rule for the instantiation with tail helping (one-word masks,
     # sets of 1,024+ members on average, unless BPT_HELP forces it)
     forced = os.environ.get("BPT_HELP")
@@ -940,6 +952,8 @@ def main() -> int:
         "traffic": traffic,
         "per_launch": {"philox_blocks": blocks, "traversal_ms": trav_s * 1e3,
                        "workgroup_size": cnt.workgroup_size, "workgroups": cnt.workgroups,
+                       "frontier_entries": cnt.frontier_entries, "live_coins": cnt.live_coins,
+                       "members": cnt.members, "algorithmic_bytes": algo_bytes,
                        "kernel_digest": kernel_digest()},
     }
     hbm_bytes = None
@@ -947,6 +961,7 @@ def main() -> int:
         hbm_bytes = traffic / trav_s
         roofline["hbm_GBps"] = hbm_bytes / 1e9
         roofline["hbm_frac_of_8TBps"] = hbm_bytes / 8e12
+        roofline["traffic_over_algorithmic"] = traffic / max(1, algo_bytes)
 
     result = {
         "metric": METRIC,

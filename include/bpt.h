@@ -250,8 +250,11 @@ int bpt_graph_info(const bpt_graph* g, uint32_t* n, uint64_t* m, uint32_t* prob_
 
 /* Frees the device memory the graph keeps cached between calls: traversal
  * workspaces and output pools (tens of GB for graphs with millions of
- * vertices).  Calls in flight on other threads keep theirs.  The next sampling
- * call allocates again.  Returns BPT_OK or BPT_EINVAL. */
+ * vertices: a workspace holds a traversal slot per resident workgroup, within
+ * 60% of the free device memory and 160 GB, or the share that the environment
+ * variable BPT_WORKSPACE_FRACTION gives).  Calls in flight on other threads
+ * keep theirs.  The next sampling call allocates again.  Returns BPT_OK or
+ * BPT_EINVAL. */
 int bpt_graph_release_cache(bpt_graph* g);
 
 /* ------------------------------------------------------------------------
@@ -455,8 +458,8 @@ typedef struct bpt_request {
 /* memory_budget: bytes of admitted work at a time (0: 8 GiB);
  * max_jobs_per_launch: requests sharing one launch at most, 0 for 256.
  * Device memory: two traversal workspaces sized for the largest graph seen
- * (about 36 bytes per vertex per resident workgroup each, from at most 60%
- * of the free memory) and their pools.  A workspace is made, or remade
+ * (about 36 bytes per vertex per resident workgroup each, within 60% of
+ * the free memory) and their pools.  A workspace is made, or remade
  * larger, by the first launch that needs it: on a 4M-vertex graph that takes
  * seconds, and requests queued meanwhile wait, so a service submits one
  * request on its largest graph at start.
@@ -512,9 +515,11 @@ uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples);
 
 /* ------------------------------------------------------------------------
  * bpt_tune_colors - launch-shape autotuner.  Times the fused traversal of
- * sample ids 0 .. min(n_samples, 4 x 64 x resident workgroups) - 1 under
- * `seed` (two runs each, HIP events, traversal plus CSR assembly) at 8, 16,
- * ..., 1024 colours per batch, then, at the fastest width, with the colour
+ * sample ids 0 .. min(n_samples, 16 x 64 x resident workgroups) - 1 under
+ * `seed` (HIP events, traversal plus CSR assembly; the best of two runs for
+ * trials under 4 x 64 samples per resident workgroup) at 8, 16, ..., 1024
+ * colours per batch, stopping once two widths in a row are at least 10%
+ * slower than the fastest so far, then, at the fastest width, with the colour
  * schedule of the expansion forced to per-coin discovery and to per-edge
  * gathering of live colours instead of the kernel's per-wavefront choice
  * (kept when 3% faster).  It remembers the result for this graph and jobs of

@@ -265,8 +265,7 @@ DevGraph dev_graph(const bpt_graph* g) {
 size_t fused_slot_bytes(uint32_t n, int nw) {
     const size_t N = n;
     size_t b = 0;
-    b += N * nw * 8;        // visited
-    b += 2 * N * nw * 8;    // frontier (two levels)
+    b += N * mask_record_words(nw) * 8;  // visited and frontier masks (two levels), per vertex
     b += (nw > 1) ? N * 4 : 0;  // stamp
     b += 2 * N * 4;         // queue
     b += N * 4;             // touched
@@ -289,8 +288,7 @@ size_t carve_fused_slots(char* base, uint32_t n, int nw, uint32_t slots, FusedSl
         return q;
     };
     FusedSlots f{};
-    f.visited = reinterpret_cast<unsigned long long*>(take(S * N * nw * 8));
-    f.frontier = reinterpret_cast<unsigned long long*>(take(S * 2 * N * nw * 8));
+    f.masks = reinterpret_cast<unsigned long long*>(take(S * N * mask_record_words(nw) * 8));
     f.stamp = reinterpret_cast<uint32_t*>(take(nw > 1 ? S * N * 4 : 4));
     f.queue = reinterpret_cast<uint32_t*>(take(S * 2 * N * 4));
     f.touched = reinterpret_cast<uint32_t*>(take(S * N * 4));
@@ -307,13 +305,18 @@ size_t carve_fused_slots(char* base, uint32_t n, int nw, uint32_t slots, FusedSl
 
 size_t unfused_slot_bytes(uint32_t n) { return bitmap_words(n) * 8 + (size_t)n * 4; }
 
-// Device memory a new workspace may take: a third of what is free (at most
-// 96 GB), or `fraction` of it (at most 160 GB) when given.
-size_t memory_budget(double fraction = 0.0) {
+// Device memory a new workspace may take: 60% of what is free, at most
+// 160 GB (BPT_WORKSPACE_FRACTION, 0 < f <= 0.9, sets the share).  Slots of
+// wide masks on large graphs are the only ones this bounds: R-MAT 22 at 128
+// colours needs 138 GB for a slot per resident workgroup.
+size_t memory_budget() {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return (size_t)8 << 30;
-    if (fraction > 0.0) return std::min((size_t)((double)free_b * fraction), (size_t)160 << 30);
-    return std::min(free_b / 3, (size_t)96 << 30);
+    double fraction = 0.6;
+    const char* v = getenv("BPT_WORKSPACE_FRACTION");
+    const double f = v ? atof(v) : 0.0;
+    if (f > 0.0 && f <= 0.9) fraction = f;
+    return std::min((size_t)((double)free_b * fraction), (size_t)160 << 30);
 }
 
 // Allocates and zeroes the traversal state of a new workspace.
@@ -333,12 +336,12 @@ uint64_t slots_wanted(const bpt_graph* g, int nw, uint64_t units) {
     return std::min(want, cap);
 }
 
-Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units, double budget_fraction = 0.0) {
+Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
     Workspace* ws = new Workspace();
     ws->nw = nw;
     try {
         const uint32_t n = g->n;
-        const size_t budget = memory_budget(budget_fraction);
+        const size_t budget = memory_budget();
         char* p;
         if (nw > 0) {
             const size_t per = fused_slot_bytes(n, nw) + 1024;
@@ -941,8 +944,7 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
         if (!l->ws || l->ws_n < owner->n) {  // slots for the largest graph so far, as many as the GPU keeps resident
             delete l->ws;
             l->ws = nullptr;
-            // a lane's launches need every resident workgroup: up to 60% of the free memory
-            l->ws = make_workspace(owner, 1, ~0ull >> 1, 0.6);
+            l->ws = make_workspace(owner, 1, ~0ull >> 1);
             l->ws_n = owner->n;
         }
         Workspace* ws = l->ws;
@@ -2000,15 +2002,20 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
         set_status(BPT_EINVAL, "n_samples must be in [1, 2^34)");
         return 0;
     }
-    // Jobs beyond four 64-colour batches per resident workgroup behave alike
-    // per batch: the trial is capped there.
-    const uint64_t S = std::min<uint64_t>(n_samples, 4 * 64 * fused_resident(gg));
+    // The trial is capped at sixteen 64-colour batches per resident workgroup:
+    // with fewer, the launch's tail (the heaviest batches running alone) weighs
+    // more than in a large job and favours narrow batches that the job would
+    // not want.
+    const uint64_t resident = fused_resident(gg);
+    const uint64_t S = std::min<uint64_t>(n_samples, 16 * 64 * resident);
+    // short trials take the best of two runs; long ones are steady in one
+    const int reps = S >= 4 * 64 * resident ? 1 : 2;
     Workspace* ws = nullptr;
-    // best of two runs (the first also loads the kernel and sizes the pool), traversal + CSR assembly
+    // traversal + CSR assembly, in HIP events (workspace and pool sizing are outside)
     auto trial = [&](uint32_t c, int gather, uint64_t* ns_out) -> int {
         ws = acquire(gg, mask_words(c), (S + c - 1) / c);
         uint64_t ns = ~0ull;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < reps; ++rep) {
             CallResult res;
             const int rc = run_sampling(gg, ws, 0, S, c, seed, 0u, nullptr, nullptr, nullptr, 0, true, false, &res,
                                         gather);
@@ -2029,12 +2036,16 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
     try {
         HIP_TRY(hipSetDevice(gg->device));
         uint64_t best_ns = ~0ull;
-        for (uint32_t c = 8; c <= 1024; c <<= 1) {  // colours per batch, under the kernel's own schedule choice
+        int worse = 0;  // widths in a row at least 10% slower than the best so far
+        for (uint32_t c = 8; c <= 1024 && worse < 2; c <<= 1) {  // under the kernel's own schedule choice
             uint64_t ns = 0;
             if (trial(c, kGatherAuto, &ns) != BPT_OK) return 0;
             if (ns < best_ns) {
                 best_ns = ns;
                 best.colors = c;
+                worse = 0;
+            } else {
+                worse = (ns * 10 >= best_ns * 11) ? worse + 1 : 0;
             }
         }
         // then the colour schedule at that width: forced either way, kept if 3% faster

@@ -230,12 +230,13 @@ struct Ctr {
     uint32_t* cnt;   // [64 * NW]
 };
 
-// Traversal state of one slot.
+// Traversal state of one slot.  A vertex's masks form one record (visited,
+// frontier of even levels, frontier of odd levels: mask_record_words(NW)
+// words), so a discovery's fetch-or on the next frontier finds the line its
+// fetch-or on visited has just brought in.
 template <int NW>
 struct BatchCtx {
-    unsigned long long* visited;    // n * NW
-    unsigned long long* frontier0;  // frontier masks of even levels
-    unsigned long long* frontier1;  // frontier masks of odd levels
+    unsigned long long* masks;  // n records
     uint32_t* stamp;
     uint32_t* queue0;   // frontier queue of even levels
     uint32_t* queue1;   // frontier queue of odd levels
@@ -243,6 +244,15 @@ struct BatchCtx {
     unsigned long long* tbits;
     uint32_t n;
     unsigned int* err;
+
+    static constexpr size_t kRec = mask_record_words(NW);
+    __device__ __forceinline__ unsigned long long* vis(uint32_t u, int k) const {
+        return masks + (size_t)u * kRec + k;
+    }
+    // frontier masks of the levels of this parity
+    __device__ __forceinline__ unsigned long long* fr(int parity, uint32_t u, int k) const {
+        return masks + (size_t)u * kRec + (size_t)(1 + parity) * NW + k;
+    }
 };
 
 // Slot arrays are strided by the largest n of the launch's graphs; b.n is set
@@ -253,9 +263,7 @@ __device__ __forceinline__ BatchCtx<NW> slot_ctx(const FusedArgs& a, uint32_t sl
     BatchCtx<NW> b;
     b.n = n;
     b.err = &a.ctl->err;
-    b.visited = a.ws.visited + (size_t)slot * n * NW;
-    b.frontier0 = a.ws.frontier + (size_t)slot * 2 * n * NW;
-    b.frontier1 = b.frontier0 + (size_t)n * NW;
+    b.masks = a.ws.masks + (size_t)slot * n * mask_record_words(NW);
     b.stamp = (NW > 1) ? a.ws.stamp + (size_t)slot * n : nullptr;
     b.queue0 = a.ws.queue + (size_t)slot * 2 * n;
     b.queue1 = b.queue0 + n;
@@ -272,12 +280,10 @@ template <int NW, bool kSh>
 __device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, const Ctr& ct, uint32_t u, int k,
                                               unsigned long long bits, int next, uint32_t qslot, uint32_t tag,
                                               uint32_t base_tag) {
-    const size_t idx = (size_t)u * NW + k;
-    const unsigned long long old = atomicOr(&b.visited[idx], bits);
+    const unsigned long long old = atomicOr(b.vis(u, k), bits);
     unsigned long long fresh = bits & ~old;
     if (!fresh) return;
-    unsigned long long* fr = next ? b.frontier1 : b.frontier0;
-    const unsigned long long old_next = atomicOr(&fr[idx], fresh);
+    const unsigned long long old_next = atomicOr(b.fr(next, u, k), fresh);
     for (unsigned long long f = fresh; f; f &= f - 1)
         atomicAdd(&ct.cnt[k * 64 + (__ffsll((long long)f) - 1)], 1u);
     bool push, first;
@@ -548,9 +554,14 @@ constexpr uint32_t kIdleRounds = 1u << 15;  // helper: rounds without an open ba
 
 // Writes each colour's members (ascending) from the sorted vertex list
 // `list[0..T)` into the pool and clears visited[] for the listed vertices.
+// With one-word masks, pass 1 keeps each listed vertex's mask at its list
+// position in the slot's queue memory (2n words, idle once the traversal has
+// ended) and clears it at once, so pass 2 reads the masks in list order
+// instead of gathering them from the vertex records a second time.
 template <int NW, int BS>
 __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW, BS>& s, const uint32_t* list,
                            uint32_t T, bool write_ok) {
+    unsigned long long* const kept = reinterpret_cast<unsigned long long*>(b.queue0);  // n entries
     constexpr int kWaves = BS / kWave;
     const uint32_t lane = lane_id();
     const uint32_t wid = threadIdx.x / kWave;
@@ -578,7 +589,16 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
         for (uint32_t r = 0; r < kB; ++r)
 #pragma unroll
             for (int k = 0; k < NW; ++k)
-                mk[r][k] = (u[r] != kNone) ? load_coherent64(&b.visited[(size_t)u[r] * NW + k]) : 0ull;
+                mk[r][k] = (u[r] != kNone) ? load_coherent64(b.vis(u[r], k)) : 0ull;
+        if constexpr (NW == 1) {
+#pragma unroll
+            for (uint32_t r = 0; r < kB; ++r) {
+                if (u[r] != kNone) {
+                    store_coherent64(&kept[(ch + r) * kWave + lane], mk[r][0]);
+                    store_coherent64(b.vis(u[r], 0), 0ull);
+                }
+            }
+        }
 #pragma unroll
         for (uint32_t r = 0; r < kB; ++r) {
 #pragma unroll
@@ -624,7 +644,9 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
         for (uint32_t r = 0; r < kB; ++r)
 #pragma unroll
             for (int k = 0; k < NW; ++k)
-                mk[r][k] = (u[r] != kNone) ? load_coherent64(&b.visited[(size_t)u[r] * NW + k]) : 0ull;
+                mk[r][k] = (u[r] == kNone) ? 0ull
+                           : (NW == 1)      ? load_coherent64(&kept[(ch + r) * kWave + lane])
+                                            : load_coherent64(b.vis(u[r], k));
 #pragma unroll
         for (uint32_t r = 0; r < kB; ++r) {
 #pragma unroll
@@ -640,9 +662,9 @@ __device__ void write_sets(uint32_t* pool, const BatchCtx<NW>& b, FusedShared<NW
                     if ((int)lane == bpos) run[k] += (unsigned long long)__popcll(bal);
                 }
             }
-            if (u[r] != kNone) {
+            if (NW > 1 && u[r] != kNone) {
 #pragma unroll
-                for (int k = 0; k < NW; ++k) store_coherent64(&b.visited[(size_t)u[r] * NW + k], 0ull);
+                for (int k = 0; k < NW; ++k) store_coherent64(b.vis(u[r], k), 0ull);
             }
         }
     }
@@ -926,7 +948,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                 // smaller than the workgroup costs every thread at most one entry, and it
                 // issues all of their loads before using any result.
                 const uint32_t npos = min((uint32_t)BS, cnt) * kEPT;  // LDS positions in use
-                unsigned long long* fr_cur = cur ? b.frontier1 : b.frontier0;
                 uint32_t vq[kEPT];
 #pragma unroll
                 for (uint32_t j = 0; j < kEPT; ++j) {
@@ -944,7 +965,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                                                    : (layout == BPT_PROB_UNIFORM ? g.thr_uniform : 0u);
 #pragma unroll
                     for (int k = 0; k < NW; ++k)
-                        mk[j][k] = ok ? atomicExch(&fr_cur[(size_t)vq[j] * NW + k], 0ull) : 0ull;
+                        mk[j][k] = ok ? atomicExch(b.fr(cur, vq[j], k), 0ull) : 0ull;
                 }
                 uint32_t my_items[kEPT];
                 uint32_t items = 0;

@@ -84,9 +84,13 @@ constexpr unsigned int kHelpStagePos = 2048;  // staged positions per chunk at m
 
 // Per-slot state of the fused traversal (one slot per resident workgroup).
 // All arrays are zero between batches except `stamp`, whose values only grow.
+// Words of a vertex's mask record in a fused slot: visited, the frontier of
+// even levels and the frontier of odd levels, NW words each; one-word records
+// are padded to 32 bytes so that none straddles a 64-byte line.
+constexpr __host__ __device__ size_t mask_record_words(int nw) { return nw == 1 ? 4 : 3 * (size_t)nw; }
+
 struct FusedSlots {
-    unsigned long long* visited;   // slots * n * NW
-    unsigned long long* frontier;  // slots * 2 * n * NW (two levels in flight)
+    unsigned long long* masks;     // slots * n * mask_record_words(NW): per-vertex mask records
     uint32_t* stamp;               // slots * n           (NW > 1 only)
     uint32_t* queue;               // slots * 2 * n
     uint32_t* touched;             // slots * n

@@ -50,15 +50,18 @@ __host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32
 #endif
 }
 
-// Ten Philox rounds on counter (c0..c3) with key (k0, k1).
+// Ten Philox rounds on counter (c0..c3) with key (k0, k1).  Each round's two
+// 32x32 products are taken whole, as 64-bit values: on gfx950 that is one
+// v_mad_u64_u32 per product (both halves) instead of a v_mul_hi_u32 and a
+// v_mul_lo_u32, and it issues at the full vector rate.
 __host__ __device__ __forceinline__ Block4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                     uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hiA = mul_hi32(kPhiloxMulA, c0);
-        const uint32_t loA = kPhiloxMulA * c0;
-        const uint32_t hiB = mul_hi32(kPhiloxMulB, c2);
-        const uint32_t loB = kPhiloxMulB * c2;
+        const uint64_t pA = (uint64_t)kPhiloxMulA * c0;
+        const uint64_t pB = (uint64_t)kPhiloxMulB * c2;
+        const uint32_t hiA = (uint32_t)(pA >> 32), loA = (uint32_t)pA;
+        const uint32_t hiB = (uint32_t)(pB >> 32), loB = (uint32_t)pB;
         c0 = xor3(hiB, c1, k0);
         c1 = loB;
         c2 = xor3(hiA, c3, k1);
