@@ -280,7 +280,12 @@ template <int NW, bool kSh>
 __device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, const Ctr& ct, uint32_t u, int k,
                                               unsigned long long bits, int next, uint32_t qslot, uint32_t tag,
                                               uint32_t base_tag) {
-    const unsigned long long old = atomicOr(b.vis(u, k), bits);
+    // Read first: a coin whose colours have all reached u already changes
+    // nothing, and a device-coherent load costs well under half a random
+    // fetch-or (bits only grow within a batch, so a set bit is never stale).
+    unsigned long long* const vp = b.vis(u, k);
+    if (!(bits & ~load_coherent64(vp))) return;
+    const unsigned long long old = atomicOr(vp, bits);
     unsigned long long fresh = bits & ~old;
     if (!fresh) return;
     const unsigned long long old_next = atomicOr(b.fr(next, u, k), fresh);
