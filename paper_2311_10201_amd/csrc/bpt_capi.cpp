@@ -495,6 +495,15 @@ uint64_t pool_estimate(bpt_graph* g, uint64_t n_samples) {
 // it, so it is used once a graph's running mean set size reaches
 // kHelpMembers; BPT_HELP=0 or 1 forces it.
 constexpr double kHelpMembers = 1024.0;
+// kJobReadFirst for jobs on this graph: sets of 1,024+ members on average,
+// as for tail helping (BPT_READ_FIRST=0/1 forces it).
+uint32_t job_flags(bpt_graph* g) {
+    const int forced = env_int("BPT_READ_FIRST", -1);
+    if (forced >= 0) return forced ? kJobReadFirst : 0u;
+    std::lock_guard<std::mutex> lk(g->mu);
+    return g->mean_members >= kHelpMembers ? kJobReadFirst : 0u;
+}
+
 bool help_wanted(bpt_graph* g) {
     const int forced = env_int("BPT_HELP", -1);
     if (forced >= 0) return forced != 0;
@@ -639,6 +648,7 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.job0.batch_begin = 0;
             a.job0.out_base = 0;
             a.job0.colors = colors;
+            a.job0.flags = job_flags(g);
             a.jobs = nullptr;
             a.n_jobs = 1;
             a.n_max = g->n;
@@ -747,6 +757,7 @@ int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<u
         fj.batch_begin = n_batches;
         fj.out_base = total_samples;
         fj.colors = colors[live[i]];
+        fj.flags = job_flags(jb.graph);
         n_batches += (jb.n_samples + fj.colors - 1) / fj.colors;
         total_samples += jb.n_samples;
     }
@@ -983,6 +994,7 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
             fj.batch_begin = b;
             fj.out_base = base;
             fj.colors = c.colors;
+            fj.flags = job_flags(c.graph);
             b += (c.n_samples + c.colors - 1) / c.colors;
             base += c.n_samples;
         }
@@ -1314,6 +1326,7 @@ int bpt_sample_rrr_noalloc(bpt_graph* g, uint64_t first_sample, uint64_t n_sampl
             a.job0.first_sample = first_sample;
             a.job0.n_samples = n_samples;
             a.job0.colors = colors;
+            a.job0.flags = job_flags(gg);
             a.n_jobs = 1;
             a.n_max = gg->n;
             a.ws = fs;
@@ -1656,6 +1669,7 @@ bpt_plan* bpt_plan_create(bpt_graph* g, uint64_t max_samples, uint32_t colors_pe
         FusedJob j = {};
         j.g = dev_graph(gg);
         j.colors = colors;
+        j.flags = job_flags(gg);  // fixed for the plan's life, from the graph's history at creation
         HIP_TRY(hipMemcpy(p->d_job, &j, sizeof(j), hipMemcpyHostToDevice));
         HIP_TRY(hipDeviceSynchronize());
         p->magic = kPlanMagic;
@@ -1816,6 +1830,7 @@ bpt_plan* bpt_jobs_plan_create(const bpt_job* jobs, uint32_t n_jobs, uint64_t po
                 fj.batch_begin = gr.n_batches;
                 fj.out_base = samples;
                 fj.colors = colors[ids[t]];
+                fj.flags = job_flags(gg);
                 gr.n_batches += (jb.n_samples + fj.colors - 1) / fj.colors;
                 samples += jb.n_samples;
                 est += pool_estimate(gg, jb.n_samples);

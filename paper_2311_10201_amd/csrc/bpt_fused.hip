@@ -244,6 +244,7 @@ struct BatchCtx {
     unsigned long long* tbits;
     uint32_t n;
     unsigned int* err;
+    bool read_first;  // the batch's job has kJobReadFirst
 
     static constexpr size_t kRec = mask_record_words(NW);
     __device__ __forceinline__ unsigned long long* vis(uint32_t u, int k) const {
@@ -263,6 +264,7 @@ __device__ __forceinline__ BatchCtx<NW> slot_ctx(const FusedArgs& a, uint32_t sl
     BatchCtx<NW> b;
     b.n = n;
     b.err = &a.ctl->err;
+    b.read_first = false;
     b.masks = a.ws.masks + (size_t)slot * n * mask_record_words(NW);
     b.stamp = (NW > 1) ? a.ws.stamp + (size_t)slot * n : nullptr;
     b.queue0 = a.ws.queue + (size_t)slot * 2 * n;
@@ -280,11 +282,12 @@ template <int NW, bool kSh>
 __device__ __forceinline__ void discover_word(const BatchCtx<NW>& b, const Ctr& ct, uint32_t u, int k,
                                               unsigned long long bits, int next, uint32_t qslot, uint32_t tag,
                                               uint32_t base_tag) {
-    // Read first: a coin whose colours have all reached u already changes
-    // nothing, and a device-coherent load costs well under half a random
-    // fetch-or (bits only grow within a batch, so a set bit is never stale).
+    // Read first (jobs with kJobReadFirst): a coin whose colours have all
+    // reached u already changes nothing, and a device-coherent load costs well
+    // under half a random fetch-or (bits only grow within a batch, so a set
+    // bit is never stale).
     unsigned long long* const vp = b.vis(u, k);
-    if (!(bits & ~load_coherent64(vp))) return;
+    if (b.read_first && !(bits & ~load_coherent64(vp))) return;
     const unsigned long long old = atomicOr(vp, bits);
     unsigned long long fresh = bits & ~old;
     if (!fresh) return;
@@ -682,6 +685,7 @@ struct BatchJob {
     uint64_t seed, first, n_samples, out_base;
     uint64_t batch;  // index within the job
     uint32_t colors;
+    uint32_t flags;
     const uint32_t* order;
 };
 
@@ -701,6 +705,7 @@ __device__ __forceinline__ BatchJob batch_job(const FusedArgs& a, uint32_t job, 
     j.n_samples = uni64(jp ? jp->n_samples : a.job0.n_samples);
     j.out_base = uni64(jp ? jp->out_base : a.job0.out_base);
     j.colors = uni32(jp ? jp->colors : a.job0.colors);
+    j.flags = uni32(jp ? jp->flags : a.job0.flags);
     j.order = uni_ptr(jp ? jp->order : a.job0.order);
     j.batch = uni64(bt) - uni64(jp ? jp->batch_begin : a.job0.batch_begin);
     return j;
@@ -755,6 +760,7 @@ __device__ void help_others(const FusedArgs& a, FusedShared<NW, BS>& s, uint32_t
         const BatchJob jb = batch_job(a, s.job, s.batch);
         BatchCtx<NW> b = slot_ctx<NW>(a, h);
         b.n = jb.g.n;
+        b.read_first = (jb.flags & kJobReadFirst) != 0;
         const unsigned long long s0 = jb.first + jb.batch * jb.colors;
         const Ctr ct{hr->qlen, &hr->tlen, s.cnt};  // colour counts kept here, added to hr->cnt per unit
         for (uint32_t c = tid; c < 64u; c += BS) s.cnt[c] = 0u;
@@ -889,6 +895,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
         const uint32_t layout = g.prob_layout;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         b.n = n;
+        b.read_first = (jb.flags & kJobReadFirst) != 0;
         // samples s0 .. s0 + ncol - 1 take colours 0 .. ncol - 1 (colors <= C per batch)
         const uint64_t s0 = first + batch * colors;
         const uint32_t ncol = (uint32_t)min((uint64_t)colors, n_samples - batch * colors);

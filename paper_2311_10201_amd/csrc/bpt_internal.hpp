@@ -109,6 +109,13 @@ struct Output {
 };
 
 // One job of a fused launch: a graph and a range of sample ids under a seed.
+// FusedJob::flags: discoveries read visited[u] before their fetch-or.  It
+// pays where most live coins find their colours there already (graphs whose
+// sets are large: dense cores reached along many paths) and costs a round
+// trip where they do not (small, tree-like sets).  The sets are the same
+// either way.
+constexpr uint32_t kJobReadFirst = 1u;
+
 struct FusedJob {
     DevGraph g;
     uint64_t seed;
@@ -117,7 +124,7 @@ struct FusedJob {
     uint64_t batch_begin;  // first launch-wide batch index of the job
     uint64_t out_base;     // position of the job's first sample in Output::counts / where
     uint32_t colors;       // samples per batch (at most 64 * NW)
-    uint32_t pad_;
+    uint32_t flags;        // kJob* bits
     const uint32_t* order; // batch composition: batch b takes samples first + order[b*colors ..] (null: in id order)
 };
 

@@ -335,6 +335,31 @@ def test_workgroup_shapes(block, monkeypatch):
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
 
 
+@pytest.mark.parametrize("force", ["0", "1"])
+def test_visited_read_first(force, monkeypatch):
+    """Discoveries with and without the read of visited[u] before the
+    fetch-or (BPT_READ_FIRST forces the per-job choice) return the oracle's
+    sets and work counters, on a graph whose colours meet at hubs so that many
+    live coins find their colour already there, under both colour schedules."""
+    n, src, dst = hub_graph(n=6_000, hubs=6, hub_in=5_000, hub_out=800, m_rand=30_000, seed=31)
+    prob = graphgen.uniform_prob(len(src), 0.05)
+    og = oracle.Graph(n, src, dst, prob)
+    S = 1200
+    ref = og.sample(41, S, nthreads=8)
+    blocks = oracle.philox_blocks(og, ref)
+    monkeypatch.setenv("BPT_READ_FIRST", force)
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    for mode in ("never", "always"):
+        monkeypatch.setenv("BPT_GATHER", mode)
+        for c in (8, 64, 256):
+            announce(f"BPT_READ_FIRST={force} BPT_GATHER={mode} C={c}")
+            off, ver, cnt = sample_device(g, 0, S, c, 41)
+            assert_same_sets(off, ver, ref, f"read first {force} {mode} C={c}")
+            assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
+            assert cnt.frontier_entries == oracle.fused_frontier_entries(ref, c)
+            assert cnt.philox_blocks == blocks
+
+
 @pytest.mark.parametrize("mode", ["never", "always"])
 @pytest.mark.parametrize("layout", ["uniform", "edge"])
 def test_colour_schedules(mode, layout, monkeypatch):
