@@ -60,6 +60,24 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kDiscQueue = 256;
 constexpr uint32_t kQuadsPerItem = 8;  // 4-edge quads one work item covers at most (one entry lookup)
 
+// Staging of large chunks orders entries by colour count: the lanes of a
+// wavefront take consecutive work items, and a lane loops over its entry's
+// colours, so a wavefront whose items mix 1-, 2- and 3-colour entries keeps
+// lanes idle for the longest (on R-MAT 22 p = 0.01 about a quarter of the
+// expansion's lane slots; with entries grouped by colour count, about 6%).
+// Buckets, in position order: 64+, 32-63, 16-31, 8-15, 4-7, 3, 2, 1 colours,
+// then entries without work items.
+constexpr uint32_t kColourBuckets = 9;
+__device__ __forceinline__ uint32_t colour_bucket(uint32_t pc) {
+    return pc == 0 ? 8u
+         : pc >= 64 ? 0u
+         : pc >= 32 ? 1u
+         : pc >= 16 ? 2u
+         : pc >= 8  ? 3u
+         : pc >= 4  ? 4u
+         : 8u - pc;  // 3 -> 5, 2 -> 6, 1 -> 7
+}
+
 // 4-edge quads per work item of an entry with pc colours: kQuadsPerItem in
 // general, 4 for entries expected to gather several live colours per edge
 // (the test of expand_item), whose quads are heavy: a finer split keeps more
@@ -116,6 +134,8 @@ struct FusedShared {
     uint16_t dq_c[BS / kWave][kDiscQueue];
     uint32_t dq_len[BS / kWave];
     uint32_t next_item;  // work items of the current chunk handed out to wavefronts so far
+    uint32_t bcnt[kColourBuckets];   // staging by colour count: entries per bucket (zero between chunks)
+    uint32_t bbase[kColourBuckets];  // ... and each bucket's first position
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
@@ -482,6 +502,31 @@ __device__ __forceinline__ void expand_item(const DevGraph& g, uint64_t seed, ui
             }
         }
     }
+}
+
+// Moves one staged field of this thread's entries (places tid*E .. tid*E+E-1)
+// to places at[0..E): all threads read, then all write.  The barrier before
+// the reads also orders them after the previous field's writes.
+template <uint32_t E, class T>
+__device__ __forceinline__ void move_staged(T* field, const uint32_t (&at)[E], uint32_t tid) {
+    T v[E];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) v[j] = field[tid * E + j];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) field[at[j]] = v[j];
+}
+template <uint32_t E, int NW>
+__device__ __forceinline__ void move_staged_mask(unsigned long long (*mask)[NW], int k, const uint32_t (&at)[E],
+                                                 uint32_t tid) {
+    unsigned long long v[E];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) v[j] = mask[tid * E + j][k];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) mask[at[j]][k] = v[j];
 }
 
 // Largest i in [0, cnt) with scan[i] <= t (scan is an exclusive prefix).
@@ -855,6 +900,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
 
     if (tid < kNumStats) s.stats[tid] = 0;
     if (tid < BS / kWave) s.dq_len[tid] = 0;
+    if (tid < kColourBuckets) s.bcnt[tid] = 0;
     if (tid == 0) {
         s.tail = 0;
         s.probes = 0;
@@ -979,7 +1025,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     for (int k = 0; k < NW; ++k)
                         mk[j][k] = ok ? atomicExch(b.fr(cur, vq[j], k), 0ull) : 0ull;
                 }
-                uint32_t my_items[kEPT];
+                uint32_t my_items[kEPT], my_pc[kEPT];
                 uint32_t items = 0;
                 unsigned long long ch_entries = 0, ch_ea = 0, ch_te = 0, ch_members = 0;
 #pragma unroll
@@ -999,6 +1045,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                     my_items[j] = item_quads(pc, rt[j], layout == BPT_PROB_EDGE, a.gather_mode) == 4u
                                       ? (quads + 3) >> 2
                                       : (quads + kQuadsPerItem - 1) / kQuadsPerItem;
+                    my_pc[j] = my_items[j] ? pc : 0u;
                     items += my_items[j];
                     s.u.st.beg[pos] = beg;
                     s.u.st.end[pos] = end;
@@ -1008,6 +1055,46 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void fu
                         ch_ea += deg;
                         ch_te += (unsigned long long)pc * deg;
                         ch_members += pc;
+                    }
+                }
+                // Chunks of at least BS entries (every position holds one) are regrouped by
+                // colour count: each entry takes a place in its bucket (an LDS atomic; the
+                // order within a bucket carries no meaning), then the staged fields move
+                // there one at a time, each read by all threads before any is overwritten.
+                const bool by_colours = cnt >= (uint32_t)BS;
+                if (by_colours) {
+                    uint32_t at[kEPT];
+#pragma unroll
+                    for (uint32_t j = 0; j < kEPT; ++j) {
+                        my_pc[j] = colour_bucket(my_pc[j]);
+                        at[j] = atomicAdd(&s.bcnt[my_pc[j]], 1u);
+                    }
+                    __syncthreads();  // bucket sizes complete
+                    if (tid == 0) {
+                        uint32_t run = 0;
+                        for (uint32_t bb = 0; bb < kColourBuckets; ++bb) {
+                            s.bbase[bb] = run;
+                            run += s.bcnt[bb];
+                            s.bcnt[bb] = 0;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (uint32_t j = 0; j < kEPT; ++j) {
+                        at[j] += s.bbase[my_pc[j]];
+                        s.u.st.scan[at[j]] = my_items[j];  // item count, until the scan below
+                    }
+                    move_staged(s.u.st.beg, at, tid);
+                    move_staged(s.u.st.end, at, tid);
+                    move_staged(s.u.st.thr, at, tid);
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) move_staged_mask(s.u.st.mask, k, at, tid);
+                    __syncthreads();
+                    items = 0;
+#pragma unroll
+                    for (uint32_t j = 0; j < kEPT; ++j) {  // the items of the entries now at this thread's places
+                        my_items[j] = s.u.st.scan[tid * kEPT + j];
+                        items += my_items[j];
                     }
                 }
                 // the chunk's staging counters, one LDS update per wavefront
