@@ -581,9 +581,12 @@ def bench_serve(args, w) -> int:
         f"({launches0:.0f} launches)")
     del off0, vert0
 
-    # one at a time: service time of each request alone
-    for r in reqs[:4]:
-        alone(r)
+    # one at a time: service time of each request alone, after two requests on
+    # every graph (the library sizes a graph's workspace from its set-size history)
+    for gi in range(len(graphs)):
+        first = next((r for r in reqs if r["gi"] == gi), None)
+        for _ in range(2 if first else 0):
+            alone(first)
     torch.cuda.synchronize()
     service = np.zeros(N)
     for i, r in enumerate(reqs):

@@ -74,6 +74,7 @@ struct TunedShape {
 // One set of traversal state + output staging; a call holds one exclusively.
 struct Workspace {
     int nw = 0;  // colour words per mask (fused), 0 = unfused
+    int block = 0;  // threads per workgroup of the fused launches it was sized for
     uint32_t slots = 0;
     bool full = false;  // as many slots as a launch on this device can use (or memory allows)
     void* slot_mem = nullptr;
@@ -139,6 +140,7 @@ struct bpt_graph {
     uint32_t magic;
     int device;
     int cus;
+    uint64_t hbm;  // device memory, bytes
     uint32_t n;
     uint64_t m;
     uint32_t layout;
@@ -211,15 +213,36 @@ int env_int(const char* name, int dflt) {
     return atoi(v);
 }
 
-// Fused workers: two 512-thread workgroups per CU, one batch each (four
-// wavefronts per SIMD), for masks of up to four words; four 256-thread
-// workgroups per CU for wider masks, whose LDS staging is larger.  A heavy
-// batch finishing alone on its CU keeps more lanes with the wider workgroup.
-// 128- and 1024-thread instantiations exist for tuning (BPT_FUSED_BLOCK).
-int fused_block(int nw) {
+// Graphs whose sets average this many members or more (running mean over the
+// graph's calls) get tail helping, the visited read before discovery
+// fetch-ors, and 512-thread workgroups.
+constexpr double kHelpMembers = 1024.0;
+
+size_t fused_slot_bytes(uint32_t n, int nw);
+
+// The graph has a set-size history and its sets are small.
+bool light_sets(const bpt_graph* g) {
+    if (!g) return false;
+    std::lock_guard<std::mutex> lk(const_cast<bpt_graph*>(g)->mu);
+    return g->mean_members > 0 && g->mean_members < kHelpMembers;
+}
+
+// Fused workers, one batch per workgroup: for masks of up to four words two
+// 512-thread workgroups per CU (four wavefronts per SIMD), where a heavy batch
+// finishing alone on its CU keeps more lanes; four 256-thread workgroups per
+// CU for graphs whose sets are small (one-word masks: twice the batches in
+// flight to hide the per-level latency of light, deep traversals; R-MAT 20 WC
+// 3.11 -> 2.80 ms) and for wider masks, whose LDS staging is larger.  128-
+// and 1024-thread instantiations exist for tuning (BPT_FUSED_BLOCK).
+int fused_block(const bpt_graph* g, int nw) {
     const int bs = env_int("BPT_FUSED_BLOCK", 0);
     if (bs == 128 || bs == 256 || (bs == 512 && nw <= 4) || (bs == 1024 && nw == 1)) return bs;
-    return nw <= 4 ? 512 : 256;
+    if (nw > 4) return 256;
+    // the doubled slot count must stay cheap: at most a fifth of the device's memory
+    // (R-MAT 20: 1,024 slots of 46 MB, 47 GB; not R-MAT 21 or 22), so that the
+    // workspaces of several cached graphs still fit side by side
+    return (nw == 1 && light_sets(g) && (uint64_t)g->cus * 4 * fused_slot_bytes(g->n, 1) <= g->hbm / 5) ? 256
+                                                                                                    : 512;
 }
 
 // Workgroups of `bs` threads resident per CU (1024 threads per CU).
@@ -240,13 +263,12 @@ uint32_t gather_mode() {
     return f >= 0 ? (uint32_t)f : kGatherAuto;
 }
 
-void fused_launch_shape(const bpt_graph* g, int nw, uint32_t slots, uint64_t n_batches, int* block, int* grid) {
-    const int bs = fused_block(nw);
+// Grid of a fused launch of `bs`-thread workgroups over `slots` slots.
+int fused_grid(const bpt_graph* g, int bs, uint32_t slots, uint64_t n_batches) {
     uint64_t gsz = std::min<uint64_t>({(uint64_t)slots, (uint64_t)g->cus * fused_per_cu(bs), n_batches});
     const int cap = env_int("BPT_FUSED_SLOTS", 0);
     if (cap > 0) gsz = std::min<uint64_t>(gsz, (uint64_t)cap);
-    *block = bs;
-    *grid = (int)std::max<uint64_t>(1, gsz);
+    return (int)std::max<uint64_t>(1, gsz);
 }
 
 DevGraph dev_graph(const bpt_graph* g) {
@@ -330,13 +352,14 @@ bool trace_on() {
 // keep busy at once, rounded up to a power of two so that workspaces are
 // reused across jobs of similar size.
 uint64_t slots_wanted(const bpt_graph* g, int nw, uint64_t units) {
-    const uint64_t cap = nw > 0 ? (uint64_t)g->cus * fused_per_cu(fused_block(nw)) : (uint64_t)g->cus * 16;
+    const uint64_t cap = nw > 0 ? (uint64_t)g->cus * fused_per_cu(fused_block(g, nw)) : (uint64_t)g->cus * 16;
     uint64_t want = 1;
     while (want < units && want < cap) want <<= 1;
     return std::min(want, cap);
 }
 
-Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
+// block: threads per workgroup of its fused launches (0: fused_block's choice).
+Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units, int block = 0) {
     Workspace* ws = new Workspace();
     ws->nw = nw;
     try {
@@ -345,7 +368,8 @@ Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units) {
         char* p;
         if (nw > 0) {
             const size_t per = fused_slot_bytes(n, nw) + 1024;
-            const size_t device_max = (size_t)(g->cus * fused_per_cu(fused_block(nw)));
+            ws->block = block > 0 ? block : fused_block(g, nw);
+            const size_t device_max = (size_t)(g->cus * fused_per_cu(ws->block));
             const size_t mem_max = std::max<size_t>(1, budget / per);
             const size_t want = std::min<size_t>(slots_wanted(g, nw, units), mem_max);
             ws->slots = (uint32_t)std::max<size_t>(1, want);
@@ -403,12 +427,15 @@ void trim_idle(bpt_graph* g, int keep_nw) {
 // (smaller idle ones of the same kind are then dropped).
 Workspace* acquire(bpt_graph* g, int nw, uint64_t units) {
     const uint64_t want = slots_wanted(g, nw, units);
+    const int block = nw > 0 ? fused_block(g, nw) : 0;
     std::vector<Workspace*> drop;
     {
         std::lock_guard<std::mutex> lk(g->mu);
         for (size_t i = 0; i < g->idle.size(); ++i) {
             Workspace* ws = g->idle[i];
-            if (ws->nw == nw && (ws->slots >= want || ws->full)) {
+            // a workspace that keeps a failed call's sets (BPT_ERANGE) is taken whatever
+            // its shape: the retry only re-assembles them
+            if (ws->nw == nw && ((ws->block == block && (ws->slots >= want || ws->full)) || ws->have_last)) {
                 g->idle.erase(g->idle.begin() + i);
                 return ws;
             }
@@ -489,12 +516,6 @@ uint64_t pool_estimate(bpt_graph* g, uint64_t n_samples) {
     return (uint64_t)est + 1024;
 }
 
-// Helping (idle workgroups joining the batches still running at the end of a
-// launch) pays when sets are large: batches have few, heavy levels and the
-// launch ends on a tail of them.  Deep traversals of small sets lose time to
-// it, so it is used once a graph's running mean set size reaches
-// kHelpMembers; BPT_HELP=0 or 1 forces it.
-constexpr double kHelpMembers = 1024.0;
 // kJobReadFirst for jobs on this graph: sets of 1,024+ members on average,
 // as for tail helping (BPT_READ_FIRST=0/1 forces it).
 uint32_t job_flags(bpt_graph* g) {
@@ -504,6 +525,11 @@ uint32_t job_flags(bpt_graph* g) {
     return g->mean_members >= kHelpMembers ? kJobReadFirst : 0u;
 }
 
+// Helping (idle workgroups joining the batches still running at the end of a
+// launch) pays when sets are large: batches have few, heavy levels and the
+// launch ends on a tail of them.  Deep traversals of small sets lose time to
+// it, so it is used once a graph's running mean set size reaches
+// kHelpMembers; BPT_HELP=0 or 1 forces it.
 bool help_wanted(bpt_graph* g) {
     const int forced = env_int("BPT_HELP", -1);
     if (forced >= 0) return forced != 0;
@@ -657,7 +683,8 @@ int run_sampling(bpt_graph* g, Workspace* ws, uint64_t first, uint64_t S, uint32
             a.ctl = ws->ctl;
             a.n_batches = (S + colors - 1) / colors;
             a.gather_mode = gather >= 0 ? (uint32_t)gather : gather_for(g, S, colors);
-            fused_launch_shape(g, ws->nw, ws->slots, a.n_batches, &block, &grid);
+            block = ws->block;
+            grid = fused_grid(g, block, ws->slots, a.n_batches);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, help_wanted(g), stream));
         } else {
             UnfusedArgs a;
@@ -784,7 +811,8 @@ int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<u
         a.n_batches = n_batches;
         a.gather_mode = gather_mode();
         int block = 256, grid = 1;
-        fused_launch_shape(owner, ws->nw, ws->slots, n_batches, &block, &grid);
+        block = ws->block;
+        grid = fused_grid(owner, block, ws->slots, n_batches);
         bool help = false;
         for (uint32_t i = 0; i < J; ++i) help = help || help_wanted(jobs[live[i]].graph);
         HIP_TRY(launch_fused(a, ws->nw, block, grid, help, stream));
@@ -853,7 +881,7 @@ int run_jobs(bpt_graph* owner, Workspace* ws, bpt_job* jobs, const std::vector<u
 // save row scans but no Philox work, while a batch occupies one workgroup).
 int size_bucket(uint64_t n_samples) { return n_samples ? 63 - __builtin_clzll(n_samples) : 0; }
 
-uint64_t fused_resident(const bpt_graph* g) { return (uint64_t)g->cus * fused_per_cu(fused_block(1)); }
+uint64_t fused_resident(const bpt_graph* g) { return (uint64_t)g->cus * fused_per_cu(fused_block(g, 1)); }
 
 // The colour schedule of a call: forced by BPT_GATHER, else the one the tuner
 // measured with these colours for this job size, else the kernel's choice.
@@ -955,7 +983,9 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
         if (!l->ws || l->ws_n < owner->n) {  // slots for the largest graph so far, as many as the GPU keeps resident
             delete l->ws;
             l->ws = nullptr;
-            l->ws = make_workspace(owner, 1, ~0ull >> 1);
+            // 512-thread workgroups whatever the graphs: a lane's launches are bounded
+            // chunks, and its slots are sized for the largest graph it has seen
+            l->ws = make_workspace(owner, 1, ~0ull >> 1, 512);
             l->ws_n = owner->n;
         }
         Workspace* ws = l->ws;
@@ -1022,7 +1052,8 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
         a.n_batches = n_batches;
         a.gather_mode = gather_mode();
         int block = 0, grid = 0;
-        fused_launch_shape(owner, 1, ws->slots, n_batches, &block, &grid);
+        block = ws->block;
+        grid = fused_grid(owner, block, ws->slots, n_batches);
         // no tail helping: idle workgroups leave at once, so that the next
         // launch (on the other lane) takes their place while this one drains
         HIP_TRY(launch_fused(a, 1, block, grid, false, l->stream));
@@ -1139,6 +1170,7 @@ bpt_graph* bpt_create_graph(uint32_t n, uint64_t m, const uint32_t* src, const u
         g->magic = kGraphMagic;
         g->device = dev;
         g->cus = prop.multiProcessorCount;
+        g->hbm = prop.totalGlobalMem;
         g->n = n;
         g->m = m;
         g->layout = csr.layout;
@@ -1297,7 +1329,8 @@ int bpt_sample_rrr_noalloc(bpt_graph* g, uint64_t first_sample, uint64_t n_sampl
         void* fin = base + ctl_b + counts_b + where_b;
         char* slot_base = base + fixed;
         const uint64_t n_batches = (n_samples + colors - 1) / colors;
-        const uint64_t device_slots = (uint64_t)gg->cus * fused_per_cu(fused_block(nw));
+        const int block_sz = fused_block(gg, nw);
+        const uint64_t device_slots = (uint64_t)gg->cus * fused_per_cu(block_sz);
         uint64_t pool_want = pool_estimate(gg, n_samples);
         for (int attempt = 0; attempt < 4; ++attempt) {
             const size_t room = kNoAllocScratchBytes - fixed;
@@ -1338,7 +1371,8 @@ int bpt_sample_rrr_noalloc(bpt_graph* g, uint64_t first_sample, uint64_t n_sampl
             a.n_batches = n_batches;
             a.gather_mode = gather_for(gg, n_samples, colors);
             int block = 0, grid = 0;
-            fused_launch_shape(gg, nw, (uint32_t)slots, n_batches, &block, &grid);
+            block = block_sz;
+            grid = fused_grid(gg, block, (uint32_t)slots, n_batches);
             HIP_TRY(launch_fused(a, nw, block, grid, help_wanted(gg), st));
             HIP_TRY(launch_finalize(counts, where, pool, n_samples, reinterpret_cast<unsigned long long*>(d_offsets),
                                     d_vertices, capacity, &ctl->total, &ctl->err, fin, fin_b, st));
@@ -1734,7 +1768,8 @@ int bpt_plan_enqueue(bpt_plan* p, uint64_t first_sample, uint64_t n_samples, uin
             a.n_batches = (n_samples + p->colors - 1) / p->colors;
             a.gather_mode = gather_for(p->graph, p->max_samples, p->colors);
             int block = 0, grid = 0;
-            fused_launch_shape(p->graph, ws->nw, ws->slots, a.n_batches, &block, &grid);
+            block = ws->block;
+            grid = fused_grid(p->graph, block, ws->slots, a.n_batches);
             HIP_TRY(launch_fused(a, ws->nw, block, grid, help_wanted(p->graph), st));
         }
         HIP_TRY(launch_finalize(ws->counts, ws->where, ws->pool, n_samples,
@@ -1897,7 +1932,8 @@ int bpt_jobs_plan_enqueue(bpt_plan* p, const uint64_t* d_params, void* stream, i
                 a.n_batches = gr.n_batches;
                 a.gather_mode = gather_mode();
                 int block = 0, grid = 0;
-                fused_launch_shape(gr.owner, gr.nw, ws->slots, gr.n_batches, &block, &grid);
+                block = ws->block;
+                grid = fused_grid(gr.owner, block, ws->slots, gr.n_batches);
                 bool help = false;
                 for (uint32_t t = 0; t < gr.n_fused; ++t) help = help || help_wanted(check_graph(gr.jobs[t].graph));
                 HIP_TRY(launch_fused(a, gr.nw, block, grid, help, st));
