@@ -519,7 +519,9 @@ uint32_t bpt_default_colors(const bpt_graph* g, uint64_t n_samples);
  * `seed` (HIP events, traversal plus CSR assembly; the best of two runs for
  * trials under 4 x 64 samples per resident workgroup) at 8, 16, ..., 1024
  * colours per batch, stopping once two widths in a row are at least 10%
- * slower than the fastest so far, then, at the fastest width, with the colour
+ * slower than the fastest so far (after an untimed pilot when the graph has
+ * no set-size history: it picks the workgroup size), then, at the fastest
+ * width, with the colour
  * schedule of the expansion forced to per-coin discovery and to per-edge
  * gathering of live colours instead of the kernel's per-wavefront choice
  * (kept when 3% faster).  It remembers the result for this graph and jobs of

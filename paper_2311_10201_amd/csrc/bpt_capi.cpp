@@ -2086,6 +2086,15 @@ uint32_t bpt_tune_colors(bpt_graph* g, uint64_t n_samples, uint64_t seed) {
     TunedShape best;
     try {
         HIP_TRY(hipSetDevice(gg->device));
+        bool no_history;
+        {
+            std::lock_guard<std::mutex> lk(gg->mu);
+            no_history = !(gg->mean_members > 0);
+        }
+        if (no_history) {  // an untimed pilot sets the set-size history, which picks the workgroup size
+            uint64_t ns = 0;
+            if (trial(64, kGatherAuto, &ns) != BPT_OK) return 0;
+        }
         uint64_t best_ns = ~0ull;
         int worse = 0;  // widths in a row at least 10% slower than the best so far
         for (uint32_t c = 8; c <= 1024 && worse < 2; c <<= 1) {  // under the kernel's own schedule choice
