@@ -386,3 +386,27 @@ def test_colour_schedules(mode, layout, monkeypatch):
         assert cnt.edge_accesses == oracle.fused_edge_accesses(og, ref, c)
         assert cnt.philox_blocks == blocks
         assert cnt.live_coins <= cnt.philox_blocks * 4
+
+
+def test_workgroup_size_follows_set_size_history(er_case, monkeypatch):
+    """A graph without set-size history runs 512-thread workgroups; once its
+    sets are known to be small it runs 256-thread ones (twice the batches in
+    flight), unless BPT_FUSED_BLOCK forces a size.  Every call returns the
+    oracle's sets."""
+    n, src, dst, prob = er_case
+    og = oracle.Graph(n, src, dst, prob)
+    S, seed = 3000, 13
+    ref = og.sample(seed, S, nthreads=8)
+    monkeypatch.delenv("BPT_FUSED_BLOCK", raising=False)
+    g = bpt.bpt_create_graph(n, src, dst, prob)
+    sizes = []
+    for i in range(3):
+        announce(f"set-size history call {i}")
+        off, ver, cnt = sample_device(g, 0, S, 64, seed)
+        assert_same_sets(off, ver, ref, f"call {i}")
+        sizes.append(cnt.workgroup_size)
+    assert sizes == [512, 256, 256]
+    monkeypatch.setenv("BPT_FUSED_BLOCK", "512")
+    off, ver, cnt = sample_device(g, 0, S, 64, seed)
+    assert_same_sets(off, ver, ref, "forced 512")
+    assert cnt.workgroup_size == 512
