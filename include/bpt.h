@@ -458,7 +458,7 @@ typedef struct bpt_request {
 /* memory_budget: bytes of admitted work at a time (0: 8 GiB);
  * max_jobs_per_launch: requests sharing one launch at most, 0 for 256.
  * Device memory: two traversal workspaces sized for the largest graph seen
- * (about 36 bytes per vertex per resident workgroup each, within 60% of
+ * (about 44 bytes per vertex per resident workgroup each, within 60% of
  * the free memory) and their pools.  A workspace is made, or remade
  * larger, by the first launch that needs it: on a 4M-vertex graph that takes
  * seconds, and requests queued meanwhile wait, so a service submits one
@@ -485,6 +485,10 @@ typedef struct bpt_server_info {
                           server's buffer)                                   */
     double batch_s;    /* current estimate of GPU seconds per 64-sample batch
                           (orders requests by deadline)                      */
+    uint32_t lane_slots;/* traversal slots of the largest lane workspace: one
+                          per resident 512-thread workgroup (two per CU),
+                          fewer when memory is short; 0 before the first
+                          launch                                             */
 } bpt_server_info;
 int bpt_server_stats(bpt_server* s, bpt_server_info* out);
 /* Serves what is queued, then stops the worker and frees the server. */

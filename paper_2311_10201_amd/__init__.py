@@ -99,7 +99,7 @@ class _Request(ctypes.Structure):
 class _ServerInfo(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("served", ctypes.c_uint64), ("busy_s", ctypes.c_double),
                 ("sample_s", ctypes.c_double), ("cover_s", ctypes.c_double), ("alloc_s", ctypes.c_double),
-                ("resampled", ctypes.c_uint64), ("batch_s", ctypes.c_double)]
+                ("resampled", ctypes.c_uint64), ("batch_s", ctypes.c_double), ("lane_slots", ctypes.c_uint32)]
 
 
 BPT_REQ_SAMPLE = 0

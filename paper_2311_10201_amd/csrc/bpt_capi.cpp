@@ -348,11 +348,11 @@ bool trace_on() {
     return on;
 }
 
-// Traversal slots a job of `units` batches (fused) or samples (unfused) can
-// keep busy at once, rounded up to a power of two so that workspaces are
-// reused across jobs of similar size.
-uint64_t slots_wanted(const bpt_graph* g, int nw, uint64_t units) {
-    const uint64_t cap = nw > 0 ? (uint64_t)g->cus * fused_per_cu(fused_block(g, nw)) : (uint64_t)g->cus * 16;
+// Traversal slots a job of `units` batches (fused, in `block`-thread
+// workgroups) or samples (unfused) can keep busy at once, rounded up to a
+// power of two so that workspaces are reused across jobs of similar size.
+uint64_t slots_wanted(const bpt_graph* g, int nw, uint64_t units, int block) {
+    const uint64_t cap = nw > 0 ? (uint64_t)g->cus * fused_per_cu(block) : (uint64_t)g->cus * 16;
     uint64_t want = 1;
     while (want < units && want < cap) want <<= 1;
     return std::min(want, cap);
@@ -371,7 +371,7 @@ Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units, int block = 0) {
             ws->block = block > 0 ? block : fused_block(g, nw);
             const size_t device_max = (size_t)(g->cus * fused_per_cu(ws->block));
             const size_t mem_max = std::max<size_t>(1, budget / per);
-            const size_t want = std::min<size_t>(slots_wanted(g, nw, units), mem_max);
+            const size_t want = std::min<size_t>(slots_wanted(g, nw, units, ws->block), mem_max);
             ws->slots = (uint32_t)std::max<size_t>(1, want);
             ws->full = want >= device_max || want >= mem_max;
             const size_t bytes = carve_fused_slots(nullptr, n, nw, ws->slots, nullptr);
@@ -382,7 +382,7 @@ Workspace* make_workspace(bpt_graph* g, int nw, uint64_t units, int block = 0) {
             const size_t per = unfused_slot_bytes(n) + 512;
             const size_t device_max = (size_t)g->cus * 16;  // wavefronts
             const size_t mem_max = std::max<size_t>(4, budget / per);
-            size_t want = std::min<size_t>(slots_wanted(g, 0, units), mem_max);
+            size_t want = std::min<size_t>(slots_wanted(g, 0, units, 0), mem_max);
             want = std::max<size_t>(4, want / 4 * 4);  // whole workgroups of 4 waves
             ws->slots = (uint32_t)want;
             ws->full = want >= device_max || want + 4 > mem_max;
@@ -426,8 +426,8 @@ void trim_idle(bpt_graph* g, int keep_nw) {
 // (unfused): an idle one with enough slots, else a new one sized to the job
 // (smaller idle ones of the same kind are then dropped).
 Workspace* acquire(bpt_graph* g, int nw, uint64_t units) {
-    const uint64_t want = slots_wanted(g, nw, units);
     const int block = nw > 0 ? fused_block(g, nw) : 0;
+    const uint64_t want = slots_wanted(g, nw, units, block);
     std::vector<Workspace*> drop;
     {
         std::lock_guard<std::mutex> lk(g->mu);
@@ -446,11 +446,11 @@ Workspace* acquire(bpt_graph* g, int nw, uint64_t units) {
     }
     for (Workspace* ws : drop) delete ws;
     try {
-        return make_workspace(g, nw, units);
+        return make_workspace(g, nw, units, block);
     } catch (const HipFail& f) {
         if (f.status != BPT_ENOMEM) throw;
         trim_idle(g, -1);  // out of device memory: drop cached workspaces of other kinds, retry once
-        return make_workspace(g, nw, units);
+        return make_workspace(g, nw, units, block);
     }
 }
 
@@ -958,6 +958,8 @@ hipStream_t lane_stream(Lane* l) { return l->stream; }
 hipEvent_t lane_done(Lane* l) { return l->done; }
 
 bool lane_finished(Lane* l) { return !l->pending || hipEventQuery(l->done) == hipSuccess; }
+
+uint32_t lane_slots(const Lane* l) { return l->ws ? l->ws->slots : 0u; }
 
 int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, std::string* why) {
     if (l->pending) {

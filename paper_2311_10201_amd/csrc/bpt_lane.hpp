@@ -44,6 +44,8 @@ int lane_launch(Lane* l, const LaneChunk* chunks, uint32_t n, hipEvent_t after, 
 hipEvent_t lane_done(Lane* l);
 // True once the current launch has completed (does not block).
 bool lane_finished(Lane* l);
+// Traversal slots of the lane's workspace (0 before its first launch).
+uint32_t lane_slots(const Lane* l);
 // Waits for the current launch.  *overflow: its output pool overflowed, so
 // the chunks' members were not written (their offsets and totals were): the
 // caller samples those requests again.  Returns a BPT_* status.

@@ -123,6 +123,7 @@ struct bpt_server {
     uint64_t launch_batches = 2048;  // batches per launch: four per workgroup the fused kernel keeps resident
     double batch_s = 2e-6;           // running estimate of the GPU time per batch (deadlines)
     uint64_t resampled = 0;          // requests sampled again alone after a pool overflow
+    uint32_t lane_slots = 0;         // traversal slots of the largest lane workspace
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_cover;
@@ -471,6 +472,7 @@ void worker_main(bpt_server* sv) {
                     std::lock_guard<std::mutex> lk(sv->mu);
                     if (sv->sampling_since < 0) sv->sampling_since = sv->now();
                     ++sv->launches;
+                    sv->lane_slots = std::max(sv->lane_slots, bpt::lane_slots(lane));
                 }
                 inflight.push_back(std::move(fl));
                 next_lane = (next_lane + 1) % kLanes;
@@ -608,6 +610,7 @@ int bpt_server_stats(bpt_server* s, bpt_server_info* out) {
     out->alloc_s = sv->t_alloc;
     out->resampled = sv->resampled;
     out->batch_s = sv->batch_s;
+    out->lane_slots = sv->lane_slots;
     return BPT_OK;
 }
 

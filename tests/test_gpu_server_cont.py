@@ -58,6 +58,9 @@ def test_request_joins_running_work():
     assert small.t_start < big.t_done and small.t_done < big.t_done
     assert seeds.t_done < big.t_done
     assert info["launches"] >= 3
+    # a lane keeps one slot per resident 512-thread workgroup, although this
+    # graph's small sets give its own calls 256-thread workgroups
+    assert info["lane_slots"] == 2 * torch.cuda.get_device_properties(0).multi_processor_count
     torch.cuda.synchronize()
     off = small.d_offsets.cpu().numpy().view(np.uint64)
     ver = small.d_vertices[:small.total].cpu().numpy().view(np.uint32)
