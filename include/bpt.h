@@ -227,7 +227,7 @@ int bpt_sample_rrr_device(bpt_graph* g, uint64_t first_sample, uint64_t n_sample
  * The sets equal those of bpt_sample_rrr_device for the same graph, range,
  * seed and colours.  The scratch bounds what one call can hold: 12 bytes per
  * sample plus the scan's temporaries, at least one traversal slot (about
- * 36 bytes per vertex for up to 64 colours, more for wider masks), and a pool
+ * 44 bytes per vertex for up to 64 colours, more for wider masks), and a pool
  * of 4 bytes per member of all the call's sets; the number of slots (batches
  * in flight) shrinks to leave the pool room.  A call that does not fit returns
  * BPT_ENOMEM with the sizes in the message and writes nothing.  Every call on a
