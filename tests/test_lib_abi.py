@@ -38,6 +38,36 @@ def test_counters_struct_matches_header():
     assert ctypes.sizeof(bpt._Counters) == 8 * len(fields)
 
 
+MIRRORED_STRUCTS = [("bpt_counters", bpt._Counters), ("bpt_job", bpt._Job), ("bpt_request", bpt._Request),
+                    ("bpt_server_info", bpt._ServerInfo)]
+
+
+def test_structs_match_header_layout(tmp_path):
+    """Every struct the binding mirrors has the header's fields in the header's
+    order, and each field sits at the offset and has the size that a C
+    compiler gives it (gcc, compiling the header as plain C)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "bpt.h"', "int main(void) {"]
+    for cname, cls in MIRRORED_STRUCTS:
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), text, re.S).group(1)
+        assert re.findall(r"(\w+)\s*;", body) == [f for f, _ in cls._fields_], cname
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{f} %zu %zu\\n", offsetof({cname}, {f}), sizeof((({cname}*)0)->{f}));')
+    lines += ["return 0;", "}"]
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", f"-I{os.path.dirname(HEADER)}", str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    got = dict(line.split(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                              text=True).stdout.splitlines())
+    for cname, cls in MIRRORED_STRUCTS:
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            desc = getattr(cls, f)
+            assert got[f"{cname}.{f}"] == f"{desc.offset} {desc.size}", (cname, f)
+
+
 def test_library_exports_every_declared_symbol():
     lib = bpt.load_library()
     for name in declared_functions():
